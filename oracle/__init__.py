@@ -1,0 +1,7 @@
+"""FP64 CPU oracle (test infrastructure only; see pd_oracle's header).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The HIP product path never does.
+"""
+from .pd_oracle import *  # noqa: F401,F403
+from .pd_oracle import __all__  # noqa: F401
