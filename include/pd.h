@@ -1,0 +1,166 @@
+/*
+ * pd.h - C ABI of the MI355X primal-dual solver for positive-contrast
+ * susceptibility MRI (dipole-kernel deconvolution with an L1 prior).
+ *
+ * Method: Wang, Cai et al., "Positive Contrast Susceptibility MR Imaging Using
+ * GPU-based Primal-Dual Algorithm", arXiv:2006.09808.  Each slice solves
+ *
+ *     min_chi  1/2 || A chi - delta ||^2 + lambda || chi ||_1,
+ *     A = F^-1 diag(D) F,   D(k) = 1/3 - (k.b)^2 / |k|^2,   D(0) = 0,
+ *
+ * (Sec. II-A, Eq. (1), with lambda on the L1 term, W = I and the L1 prior on
+ * chi itself) by the first-order primal-dual iteration of the paper's PD
+ * pseudocode: dual prox, primal prox (soft threshold), over-relaxation.
+ * Slices of a volume are independent 2-D problems (Sec. II-C, strategy (2));
+ * the 2-D kernel is the dipole kernel at k_z = 0 on the unshifted DFT grid
+ * k_i = i/(n d) (i < ceil(n/2)), else (i - n)/(n d); on an even grid with an
+ * oblique in-plane B0 it is averaged between k and -k so A stays real.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays are [nz][ny][nx], x fastest, densely packed, device memory of
+ *     the context's device.  FP32 unless the context precision is PD_FP64.
+ *   - No exceptions cross the ABI.  Every function returns a pd_status.
+ *   - Calls on one context are serialised internally and may come from any
+ *     host thread.  All GPU work of a context runs on its stream.
+ *   - The caller owns every pointer it passes (arena, delta, chi); the
+ *     library never frees them.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pd_status;
+
+enum {
+  PD_OK = 0,
+  PD_PENDING = 1,          /* ticket not finished (pd_poll timeout)               */
+  PD_ERR_ARG = -1,         /* null pointer, bad enum, non-finite parameter, ...   */
+  PD_ERR_SIZE = -2,        /* nx or ny not in the supported set, nz < 1          */
+  PD_ERR_STEP = -3,        /* tau*sigma*max|D|^2 >= 1, theta outside [0, 1], ... */
+  PD_ERR_BUDGET = -4,      /* request can never fit in the context's arena       */
+  PD_ERR_NONFINITE = -5,   /* a non-finite value appeared in the duality gap     */
+  PD_ERR_HIP = -6,         /* HIP runtime error; the context is unusable         */
+  PD_ERR_CANCELLED = -7,   /* request cancelled by pd_destroy                    */
+  PD_ERR_TICKET = -8,      /* unknown (or already reported) ticket               */
+  PD_ERR_NODEVICE = -9     /* no usable GPU                                       */
+};
+
+enum { PD_FP32 = 0, PD_FP64 = 1 };                      /* pd_config.precision */
+enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1 };  /* pd_request.kernel   */
+
+/* pd_config.flags */
+enum {
+  PD_FLAG_TIME_KERNELS = 1   /* time every launch of the iteration kernels with
+                                HIP events on the context stream (pd_kernel_time) */
+};
+
+typedef struct pd_ctx pd_ctx;     /* opaque, library-owned */
+
+typedef struct {
+  int device;          /* HIP device ordinal                                      */
+  void* stream;        /* hipStream_t to run on; NULL: the library creates one    */
+  void* arena;         /* caller-owned device memory; all per-request state and
+                          tables are carved from it.  Its size is the HBM budget
+                          under which requests are admitted.                       */
+  size_t arena_bytes;
+  int max_slots;       /* most requests resident on the GPU at once; 0 = no cap  */
+  int precision;       /* PD_FP32 (default) or PD_FP64                            */
+  int step_iters;      /* iterations launched between host scheduling points;
+                          0 = default (10)                                         */
+  int flags;           /* PD_FLAG_* */
+} pd_config;
+
+/* One reconstruction: a volume of nz slices of ny x nx voxels (Eq. (1)). */
+typedef struct {
+  int nx, ny, nz;      /* nx, ny in {8,16,24,32,48,64,96,128,192,256,384,512}   */
+  double b0[3];        /* B0 direction in voxel axes (x, y, z); any non-zero scale */
+  double voxel[2];     /* in-plane voxel size (dx, dy), any positive unit          */
+  int kernel;          /* PD_KERNEL_DIPOLE, or PD_KERNEL_IDENTITY (D = 1)          */
+  double lambda;       /* weight of the L1 term (> 0)                              */
+  double tau, sigma;   /* primal and dual step sizes (PD pseudocode, step 1)       */
+  double theta;        /* over-relaxation in [0, 1]                                */
+  int max_iter;        /* iteration cap N (pseudocode step 5), >= 0                */
+  double gap_tol;      /* stop at the first check with relgap <= gap_tol; 0: run
+                          exactly max_iter iterations                               */
+  int check_every;     /* check cadence in iterations when gap_tol > 0 (>= 1)      */
+  const void* delta;   /* field map [nz][ny][nx]; must stay valid and unchanged
+                          until the ticket completes                               */
+  void* chi;           /* output [nz][ny][nx]; written once, at completion         */
+} pd_request;
+
+typedef struct {
+  pd_status status;    /* PD_OK, PD_ERR_NONFINITE, PD_ERR_CANCELLED or PD_ERR_HIP */
+  int iterations;      /* updates applied; chi holds chi_iterations                */
+  double primal;       /* P    = sum 1/2||A chi - delta||^2 + lambda ||chi||_1     */
+  double dual;         /* Dual = sum -1/2 s^2||y||^2 - s <y, delta>,
+                          s = min(1, lambda / max|A y|)                            */
+  double rel_gap;      /* (P - Dual) / max(P, 1e-300), FP64 reductions             */
+  double t_submit, t_start, t_done;   /* seconds on pd_now()'s clock              */
+} pd_result;
+
+/* Create a context on cfg->device.  The arena must be device memory of that
+ * device of at least arena_bytes and stay allocated until pd_destroy returns.
+ * Errors: PD_ERR_ARG (null/invalid field), PD_ERR_NODEVICE, PD_ERR_HIP. */
+pd_status pd_create(const pd_config* cfg, pd_ctx** out);
+
+/* Submit n requests; never blocks on the GPU.  On PD_OK tickets[0..n-1] hold
+ * one ticket per request, and each request is admitted as soon as a slot and
+ * enough arena are free (FIFO), then iterated together with every other
+ * resident request.  Validation is all-or-nothing: on an error no request of
+ * the batch is queued and the status names the first failing check
+ * (PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET, PD_ERR_HIP). */
+pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* tickets);
+
+/* Wait up to timeout_ms (< 0: forever, 0: just look) for a ticket.  Returns
+ * PD_PENDING while it runs; once finished, fills *out (if non-null), returns
+ * out->status and forgets the ticket (a second poll gives PD_ERR_TICKET). */
+pd_status pd_poll(pd_ctx* c, uint64_t ticket, pd_result* out, int timeout_ms);
+
+/* Cancel queued and running requests (their tickets end PD_ERR_CANCELLED and
+ * their chi is left unwritten), wait for the GPU, free library resources.
+ * The arena stays the caller's.  Accepts NULL. */
+pd_status pd_destroy(pd_ctx* c);
+
+/* Static, human-readable name of a status. */
+const char* pd_status_string(pd_status s);
+
+/* Pure host check of one request, no GPU involved: the same validation
+ * pd_solve_batch applies (except the arena size).  If state_bytes is non-null
+ * it receives the arena bytes the request occupies while resident. */
+pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes);
+
+/* Largest |D(k)| of the request's kernel grid (||A||_2), computed in FP64 on
+ * the host; the step condition is tau*sigma*norm^2 < 1. */
+pd_status pd_kernel_norm(const pd_request* r, double* norm);
+
+/* Forward operator on the device: out = A in for every slice of a
+ * [nz][ny][nx] stack (the dipole field of a susceptibility map, Eq. (1)
+ * operator D).  Uses r's nx, ny, nz, b0, voxel and kernel; delta is the input,
+ * chi the output (they may not alias).  Needs arena space like a solve of the
+ * same shape; runs on the context stream and returns when out is written. */
+pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r);
+
+/* Seconds on a monotonic clock (the clock of pd_result's time stamps). */
+double pd_now(void);
+
+/* With PD_FLAG_TIME_KERNELS: number of launches and summed HIP-event time in
+ * milliseconds of one kernel class since the last reset.  kind: 0 = column
+ * kernel (forward column FFT, dual prox, inverse column FFT), 1 = row kernel
+ * (inverse row FFT, primal prox, over-relaxation, forward row FFT).
+ * pd_kernel_time_reset clears both. */
+pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms);
+pd_status pd_kernel_time_reset(pd_ctx* c);
+
+/* Bytes of arena currently in use and the number of resident requests. */
+pd_status pd_arena_usage(pd_ctx* c, size_t* used, int* resident, int* queued);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PD_H */

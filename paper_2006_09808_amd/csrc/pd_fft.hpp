@@ -1,0 +1,410 @@
+// pd_fft.hpp - register/LDS building blocks of the batched mixed-radix FFT
+// used by every transform of the primal-dual iteration (gfx950, wave64).
+//
+// A length-N transform runs as a sequence of Stockham autosort passes.  A
+// pass of radix Q after passes whose radices multiply to p takes, for each
+// butterfly j in [0, N/Q), the Q inputs at j + r N/Q, multiplies input r by
+// w^(r k) (k = j mod p, w = exp(s 2 pi i / (p Q)), s = -1 forward, +1
+// inverse), applies a Q-point DFT in registers and writes output r to
+// (j - k) Q + k + r p.  The first pass therefore reads at stride N/Q and the
+// last pass writes at stride N/Q, both with consecutive butterflies at
+// consecutive addresses, so a transform reads its input from and writes its
+// output to global memory in coalesced order and only the passes in between
+// go through LDS.  Running the passes of a forward transform in the reverse
+// order of the inverse's makes one transform's output registers exactly the
+// next transform's input registers, which is how the kernels fuse an inverse
+// FFT, a point-wise update and a forward FFT without an LDS round trip.
+//
+// Small DFTs (2, 3, 4) are written out; larger register DFTs are built as
+// A x B Cooley-Tukey products with compile-time twiddles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+#include <utility>
+
+namespace pdk {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T x, T y) {
+  cpx<T> r;
+  r.x = x;
+  r.y = y;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scl(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// multiply by DIR * i  (DIR = -1: by -i; DIR = +1: by +i)
+template <int DIR, typename T>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) {
+  if constexpr (DIR < 0) return mk(a.y, -a.x);
+  else return mk(-a.y, a.x);
+}
+
+// ---------------------------------------------------------------------------
+// compile-time trigonometry (Taylor series on a reduced argument)
+// ---------------------------------------------------------------------------
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double ce_sin_red(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int n = 1; n <= 30; ++n) {
+    term *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double ce_cos_red(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int n = 1; n <= 30; ++n) {
+    term *= -x2 / ((2.0 * n - 1.0) * (2.0 * n));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi m / R, argument reduced to (-pi, pi]
+constexpr double ce_cos_frac(int m, int R) {
+  m %= R;
+  if (m < 0) m += R;
+  if (2 * m > R) m -= R;
+  return ce_cos_red(2.0 * kPi * m / R);
+}
+constexpr double ce_sin_frac(int m, int R) {
+  m %= R;
+  if (m < 0) m += R;
+  if (2 * m > R) m -= R;
+  return ce_sin_red(2.0 * kPi * m / R);
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// a * w^m with w = exp(DIR 2 pi i / R), m and R compile-time
+template <int R, int M, int DIR, typename T>
+__device__ __forceinline__ cpx<T> twc(cpx<T> a) {
+  constexpr int m = ((M % R) + R) % R;
+  if constexpr (m == 0) {
+    return a;
+  } else if constexpr (2 * m == R) {
+    return mk(-a.x, -a.y);
+  } else if constexpr (4 * m == R) {
+    return mul_i<DIR>(a);
+  } else if constexpr (4 * m == 3 * R) {
+    return mul_i<-DIR>(a);
+  } else {
+    constexpr T c = (T)ce_cos_frac(m, R);
+    constexpr T s = (T)(DIR * ce_sin_frac(m, R));
+    return mk(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// register DFTs, natural order in and out, unnormalised
+// ---------------------------------------------------------------------------
+template <int R, int DIR, typename T>
+struct Dft;
+
+template <int A, int B, int DIR, typename T>
+__device__ __forceinline__ void dft_ab(cpx<T>* x);
+
+template <int DIR, typename T>
+struct Dft<1, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>*) {}
+};
+template <int DIR, typename T>
+struct Dft<2, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) {
+    cpx<T> a = x[0], b = x[1];
+    x[0] = a + b;
+    x[1] = a - b;
+  }
+};
+template <int DIR, typename T>
+struct Dft<3, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) {
+    constexpr T c = (T)-0.5;
+    constexpr T s = (T)(DIR * 0.866025403784438646763723170752936183);  // DIR sin(2pi/3)
+    cpx<T> t1 = x[1] + x[2], t2 = x[1] - x[2];
+    cpx<T> m = mk(x[0].x + c * t1.x, x[0].y + c * t1.y);
+    cpx<T> r = mk(-s * t2.y, s * t2.x);  // i s t2
+    x[0] = x[0] + t1;
+    x[1] = m + r;
+    x[2] = m - r;
+  }
+};
+template <int DIR, typename T>
+struct Dft<4, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) {
+    cpx<T> a0 = x[0] + x[2], a1 = x[0] - x[2];
+    cpx<T> b0 = x[1] + x[3], b1 = mul_i<DIR>(x[1] - x[3]);
+    x[0] = a0 + b0;
+    x[2] = a0 - b0;
+    x[1] = a1 + b1;
+    x[3] = a1 - b1;
+  }
+};
+template <int DIR, typename T>
+struct Dft<6, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) { dft_ab<2, 3, DIR, T>(x); }
+};
+template <int DIR, typename T>
+struct Dft<8, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) { dft_ab<2, 4, DIR, T>(x); }
+};
+template <int DIR, typename T>
+struct Dft<12, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) { dft_ab<4, 3, DIR, T>(x); }
+};
+template <int DIR, typename T>
+struct Dft<16, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) { dft_ab<4, 4, DIR, T>(x); }
+};
+template <int DIR, typename T>
+struct Dft<24, DIR, T> {
+  static __device__ __forceinline__ void run(cpx<T>* x) { dft_ab<8, 3, DIR, T>(x); }
+};
+
+// R = A B: B-point DFTs over x[a + A b], twiddle w_R^(a kb), A-point DFTs,
+// output index kb + B ka.
+template <int A, int B, int DIR, typename T>
+__device__ __forceinline__ void dft_ab(cpx<T>* x) {
+  constexpr int R = A * B;
+  cpx<T> y[R];
+  static_for<0, A>([&](auto ia) {
+    constexpr int a = decltype(ia)::value;
+    cpx<T> t[B];
+    static_for<0, B>([&](auto ib) {
+      constexpr int b = decltype(ib)::value;
+      t[b] = x[a + A * b];
+    });
+    Dft<B, DIR, T>::run(t);
+    static_for<0, B>([&](auto ik) {
+      constexpr int kb = decltype(ik)::value;
+      y[a * B + kb] = twc<R, a * kb, DIR>(t[kb]);
+    });
+  });
+  static_for<0, B>([&](auto ik) {
+    constexpr int kb = decltype(ik)::value;
+    cpx<T> t[A];
+    static_for<0, A>([&](auto ia) {
+      constexpr int a = decltype(ia)::value;
+      t[a] = y[a * B + kb];
+    });
+    Dft<A, DIR, T>::run(t);
+    static_for<0, A>([&](auto ia) {
+      constexpr int ka = decltype(ia)::value;
+      x[kb + B * ka] = t[ka];
+    });
+  });
+}
+
+// ---------------------------------------------------------------------------
+// per-length pass plans (radices in inverse-transform order; the forward
+// transform runs them reversed)
+// ---------------------------------------------------------------------------
+template <int N>
+struct Plan;
+#define PD_PLAN(N_, M_, A_, B_, C_)                              \
+  template <>                                                    \
+  struct Plan<N_> {                                              \
+    static constexpr int M = M_;                                 \
+    static constexpr int r(int i) { return i == 0 ? A_ : i == 1 ? B_ : C_; } \
+  };
+PD_PLAN(8, 1, 8, 1, 1)
+PD_PLAN(16, 1, 16, 1, 1)
+PD_PLAN(24, 2, 8, 3, 1)
+PD_PLAN(32, 2, 8, 4, 1)
+PD_PLAN(48, 2, 16, 3, 1)
+PD_PLAN(64, 2, 8, 8, 1)
+PD_PLAN(96, 2, 8, 12, 1)
+PD_PLAN(128, 2, 16, 8, 1)
+PD_PLAN(192, 2, 16, 12, 1)
+PD_PLAN(256, 2, 16, 16, 1)
+PD_PLAN(384, 2, 16, 24, 1)
+PD_PLAN(512, 3, 8, 8, 8)
+#undef PD_PLAN
+
+// radix of the i-th executed pass: inverse runs r(0..M-1), forward r(M-1..0)
+template <int N, int DIR>
+constexpr int pass_radix(int i) {
+  return DIR > 0 ? Plan<N>::r(i) : Plan<N>::r(Plan<N>::M - 1 - i);
+}
+// product of the radices executed before pass i
+template <int N, int DIR>
+constexpr int pass_prod(int i) {
+  int p = 1;
+  for (int t = 0; t < i; ++t) p *= pass_radix<N, DIR>(t);
+  return p;
+}
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// Batched FFT engine: S sequences of length N per workgroup of NT threads.
+// COLS = true: sequence index fastest across threads (column strips, element
+// n of sequence s at lds[n*(S+1)+s]); COLS = false: element index fastest
+// (rows, lds[s*LDN + n + n/32]).  Butterfly w of a pass with N/Q butterflies
+// per sequence belongs to thread w mod NT.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int S, int NT, bool COLS>
+struct Fft {
+  static constexpr int LDN = N + N / 32 + 1;                 // padded row (rows layout)
+  static constexpr int LDS_ELEMS = COLS ? N * (S + 1) : S * LDN;
+
+  static __device__ __forceinline__ int lidx(int s, int n) {
+    if constexpr (COLS) return n * (S + 1) + s;
+    else return s * LDN + n + (n >> 5);
+  }
+  template <int Q>
+  static __device__ __forceinline__ void coords(int w, int& s, int& j) {
+    constexpr int J = N / Q;
+    if constexpr (COLS) {
+      s = w % S;
+      j = w / S;
+    } else {
+      s = w / J;
+      j = w % J;
+    }
+  }
+  template <int Q>
+  static constexpr int nbutter() { return S * (N / Q); }
+  template <int Q>
+  static constexpr int nq() { return cdiv(S * (N / Q), NT); }
+
+  // twiddle r*k of a pass with product p and radix Q, from the forward
+  // table tw[m] = exp(-2 pi i m / N); conjugated for the inverse.
+  template <int DIR, int P, int Q>
+  static __device__ __forceinline__ cpx<T> tw_mul(cpx<T> a, const cpx<T>* __restrict__ tw, int r, int k) {
+    constexpr int stride = N / (P * Q);
+    cpx<T> w = tw[r * k * stride];
+    if constexpr (DIR > 0) return cmulc(a, w);
+    else return cmul(a, w);
+  }
+
+  // first pass (p = 1, no twiddles): v holds inputs at j + r N/Q; DFT and
+  // store the Stockham outputs to LDS.
+  template <int DIR, int Q>
+  static __device__ __forceinline__ void first_to_lds(cpx<T> (&v)[nq<Q>()][Q], cpx<T>* lds, int tid) {
+#pragma unroll
+    for (int q = 0; q < nq<Q>(); ++q) {
+      int w = tid + q * NT;
+      if (nbutter<Q>() % NT == 0 || w < nbutter<Q>()) {
+        int s, j;
+        coords<Q>(w, s, j);
+        Dft<Q, DIR, T>::run(v[q]);
+#pragma unroll
+        for (int r = 0; r < Q; ++r) lds[lidx(s, j * Q + r)] = v[q][r];
+      }
+    }
+  }
+
+  // a pass after the first: read LDS, twiddle, DFT; if LAST keep the
+  // outputs (positions j + r N/Q) in v, else write them back to LDS.
+  template <int DIR, int PI, bool LAST>
+  static __device__ __forceinline__ void pass_from_lds(cpx<T> (&v)[nq<pass_radix<N, DIR>(PI)>()][pass_radix<N, DIR>(PI)],
+                                                       cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid) {
+    constexpr int Q = pass_radix<N, DIR>(PI);
+    constexpr int P = pass_prod<N, DIR>(PI);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < nq<Q>(); ++q) {
+      int w = tid + q * NT;
+      if (nbutter<Q>() % NT == 0 || w < nbutter<Q>()) {
+        int s, j;
+        coords<Q>(w, s, j);
+#pragma unroll
+        for (int r = 0; r < Q; ++r) v[q][r] = lds[lidx(s, j + r * (N / Q))];
+      }
+    }
+    if constexpr (!LAST) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < nq<Q>(); ++q) {
+      int w = tid + q * NT;
+      if (nbutter<Q>() % NT == 0 || w < nbutter<Q>()) {
+        int s, j;
+        coords<Q>(w, s, j);
+        int k = j % P;
+#pragma unroll
+        for (int r = 1; r < Q; ++r) v[q][r] = tw_mul<DIR, P, Q>(v[q][r], tw, r, k);
+        Dft<Q, DIR, T>::run(v[q]);
+        if constexpr (!LAST) {
+#pragma unroll
+          for (int r = 0; r < Q; ++r) lds[lidx(s, (j - k) * Q + k + r * P)] = v[q][r];
+        }
+      }
+    }
+  }
+
+  static constexpr int M = Plan<N>::M;
+  template <int DIR>
+  static constexpr int QF() { return pass_radix<N, DIR>(0); }
+  template <int DIR>
+  static constexpr int QL() { return pass_radix<N, DIR>(M - 1); }
+
+  // Whole transform: `in` holds the inputs of the first pass (positions
+  // j + r N/QF), `out` receives the outputs of the last pass (positions
+  // j + r N/QL).  in and out may be the same array when QF == QL.  Starts
+  // with a barrier-free LDS write, so the caller must have synchronised
+  // any earlier LDS readers (call sync_before_reuse()).
+  template <int DIR>
+  static __device__ __forceinline__ void run(cpx<T> (&in)[nq<QF<DIR>()>()][QF<DIR>()],
+                                             cpx<T> (&out)[nq<QL<DIR>()>()][QL<DIR>()],
+                                             cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid) {
+    if constexpr (M == 1) {
+#pragma unroll
+      for (int q = 0; q < nq<QF<DIR>()>(); ++q) {
+        Dft<QF<DIR>(), DIR, T>::run(in[q]);
+#pragma unroll
+        for (int r = 0; r < QF<DIR>(); ++r) out[q][r] = in[q][r];
+      }
+    } else {
+      first_to_lds<DIR, QF<DIR>()>(in, lds, tid);
+      if constexpr (M == 3) {
+        constexpr int Q1 = pass_radix<N, DIR>(1);
+        cpx<T> mid[nq<Q1>()][Q1];
+        pass_from_lds<DIR, 1, false>(mid, lds, tw, tid);
+      }
+      pass_from_lds<DIR, M - 1, true>(out, lds, tw, tid);
+    }
+  }
+
+  static __device__ __forceinline__ void sync_before_reuse() {
+    if constexpr (M > 1) __syncthreads();
+  }
+
+  // position (sequence, element) of register (q, r) of a first/last pass
+  // with radix Q
+  template <int Q>
+  static __device__ __forceinline__ bool pos(int tid, int q, int r, int& s, int& n) {
+    int w = tid + q * NT;
+    int j;
+    coords<Q>(w, s, j);
+    n = j + r * (N / Q);
+    return nbutter<Q>() % NT == 0 || w < nbutter<Q>();
+  }
+};
+
+}  // namespace pdk

@@ -1,0 +1,1033 @@
+// pd_host.cpp - the C ABI: validation, arena allocation, per-shape kernel
+// tables, and the scheduler that iterates every resident request together.
+//
+// Execution model (one context = one device stream + one worker thread):
+//   pd_solve_batch validates and queues requests.  The worker admits queued
+//   requests in FIFO order while a slot and arena space are free, runs their
+//   set-up (F delta, zeroed state), then advances all resident requests by a
+//   "step" of K iterations: per iteration one column-kernel and one row-kernel
+//   launch per distinct slice shape, covering every pair of every resident
+//   volume of that shape, plus the gap check kernels on check iterations.
+//   Check results decide on the device whether a volume stops (kernels skip
+//   stopped volumes), and the host retires stopped volumes at step end:
+//   chi is unpacked into the caller's buffer, the arena space and slot are
+//   released, and the next queued requests are admitted.  Every resident
+//   volume keeps its primal, dual and exchange state in the arena between
+//   steps (the paper's device residency, Sec. II-D).
+#include "pd.h"
+#include "pd_internal.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+using namespace pdk;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultSlots = 256;
+constexpr int kMaxStep = 64;   // check_mask has 64 bits
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline bool isfin(double x) { return std::isfinite(x); }
+
+double now_s() {
+  using namespace std::chrono;
+  return duration_cast<duration<double>>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// dipole kernel grid (Eq. (1), operator D), FP64 on the host
+// ---------------------------------------------------------------------------
+double kfreq(int i, int n, double d) {
+  int half = (n + 1) / 2;
+  return (double)(i < half ? i : i - n) / ((double)n * d);
+}
+
+bool unit_b0(const double b[3], double out[3]) {
+  double nb = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+  if (!isfin(nb) || nb == 0.0) return false;
+  for (int i = 0; i < 3; ++i) out[i] = b[i] / nb;
+  return true;
+}
+
+// D[ky][kx] = 1/3 - (k.b)^2/|k|^2, D(0) = 0, averaged between k and -k
+void dipole_grid(int nx, int ny, const double b[3], const double vox[2], int kernel,
+                 std::vector<double>& D) {
+  D.assign((size_t)nx * ny, 1.0);
+  if (kernel == PD_KERNEL_IDENTITY) return;
+  double bu[3];
+  unit_b0(b, bu);
+  auto f = [&](double kx, double ky) {
+    double k2 = kx * kx + ky * ky;
+    if (k2 == 0.0) return 0.0;
+    double kb = kx * bu[0] + ky * bu[1];
+    return 1.0 / 3.0 - kb * kb / k2;
+  };
+  for (int j = 0; j < ny; ++j) {
+    double ky = kfreq(j, ny, vox[1]), kym = kfreq((ny - j) % ny, ny, vox[1]);
+    for (int i = 0; i < nx; ++i) {
+      double kx = kfreq(i, nx, vox[0]), kxm = kfreq((nx - i) % nx, nx, vox[0]);
+      D[(size_t)j * nx + i] = 0.5 * (f(kx, ky) + f(kxm, kym));
+    }
+  }
+}
+
+double grid_norm(const std::vector<double>& D) {
+  double m = 0.0;
+  for (double d : D) m = std::max(m, std::fabs(d));
+  return m;
+}
+
+// exp(-2 pi i m / n) for m < n, with the angle reduced to (-pi, pi]
+void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(n);
+  im.resize(n);
+  const double pi = 3.14159265358979323846264338327950288;
+  for (int m = 0; m < n; ++m) {
+    int mm = (2 * m > n) ? m - n : m;
+    double a = 2.0 * pi * (double)mm / (double)n;
+    re[m] = std::cos(a);
+    im[m] = -std::sin(a);
+  }
+}
+
+// work decomposition (must match the kernel instantiations)
+int rows_per_wg(int nx, int ny, int precision) {
+  if (precision == PD_FP64) return 8;
+  int s = 8;
+  while (s < 64 && 2 * s * nx <= 4096) s *= 2;
+  return (ny % s == 0) ? s : 8;
+}
+int cols_per_wg(int nx, int /*ny*/, int precision) {
+  if (precision == PD_FP64) return 8;
+  return (nx % 16 == 0) ? 16 : 8;
+}
+
+struct Layout {
+  int P, rows, cols, row_groups, col_groups;
+  size_t field;                     // one [P][ny][nx] complex buffer
+  size_t off_chi, off_yhat, off_dhat, off_ex, off_ex2, off_prow, off_pcol;
+  size_t total;
+  bool separate_ex2;
+};
+
+Layout layout_of(const pd_request& r, int precision) {
+  Layout L{};
+  size_t esz = precision == PD_FP64 ? 16 : 8;
+  L.P = (r.nz + 1) / 2;
+  L.rows = rows_per_wg(r.nx, r.ny, precision);
+  L.cols = cols_per_wg(r.nx, r.ny, precision);
+  L.row_groups = r.ny / L.rows;
+  L.col_groups = r.nx / L.cols;
+  L.field = align_up((size_t)L.P * r.nx * r.ny * esz);
+  L.separate_ex2 = r.gap_tol > 0.0;
+  size_t o = 0;
+  L.off_chi = o; o += L.field;
+  L.off_yhat = o; o += L.field;
+  L.off_dhat = o; o += L.field;
+  L.off_ex = o; o += L.field;
+  if (L.separate_ex2) { L.off_ex2 = o; o += L.field; } else { L.off_ex2 = L.off_ex; }
+  L.off_prow = o; o += align_up((size_t)L.P * L.row_groups * 2 * sizeof(double));
+  L.off_pcol = o; o += align_up((size_t)L.P * L.col_groups * 3 * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+size_t table_bytes(int nx, int ny, int precision) {
+  size_t t = precision == PD_FP64 ? 8 : 4;
+  return align_up((size_t)nx * ny * t) + align_up((size_t)nx * 2 * t) + align_up((size_t)ny * 2 * t);
+}
+
+pd_status validate(const pd_request* r, int precision, double* norm_out) {
+  if (!r) return PD_ERR_ARG;
+  if (precision != PD_FP32 && precision != PD_FP64) return PD_ERR_ARG;
+  if (!size_supported(r->nx) || !size_supported(r->ny) || r->nz < 1) return PD_ERR_SIZE;
+  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
+  double bu[3];
+  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
+  if (!isfin(r->voxel[0]) || !isfin(r->voxel[1]) || r->voxel[0] <= 0 || r->voxel[1] <= 0)
+    return PD_ERR_ARG;
+  if (!isfin(r->lambda) || r->lambda < 0) return PD_ERR_ARG;
+  if (r->max_iter < 0) return PD_ERR_ARG;
+  if (!isfin(r->gap_tol) || r->gap_tol < 0) return PD_ERR_ARG;
+  if (r->gap_tol > 0 && r->check_every < 1) return PD_ERR_ARG;
+  if (!r->delta || !r->chi) return PD_ERR_ARG;
+  if (!isfin(r->tau) || !isfin(r->sigma) || r->tau <= 0 || r->sigma <= 0) return PD_ERR_STEP;
+  if (!isfin(r->theta) || r->theta < 0 || r->theta > 1) return PD_ERR_STEP;
+  std::vector<double> D;
+  dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
+  double L = grid_norm(D);
+  if (!(r->tau * r->sigma * L * L < 1.0)) return PD_ERR_STEP;
+  if (norm_out) *norm_out = L;
+  return PD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// first-fit arena allocator over the caller's device memory
+// ---------------------------------------------------------------------------
+class Arena {
+ public:
+  void init(char* base, size_t size) {
+    base_ = base;
+    size_ = size;
+    free_.clear();
+    if (size) free_[0] = size;
+    used_ = 0;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        size_t o = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[o + bytes] = len - bytes;
+        used_ += bytes;
+        *off = o;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(std::max<size_t>(bytes, 1));
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  char* ptr(size_t off) const { return base_ + off; }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t size_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+// per kernel shape: D grid and the twiddles of both axes, in the arena
+struct TableKey {
+  int nx, ny, kernel;
+  double b[3], vox[2];
+  bool operator<(const TableKey& o) const {
+    if (nx != o.nx) return nx < o.nx;
+    if (ny != o.ny) return ny < o.ny;
+    if (kernel != o.kernel) return kernel < o.kernel;
+    for (int i = 0; i < 3; ++i)
+      if (b[i] != o.b[i]) return b[i] < o.b[i];
+    for (int i = 0; i < 2; ++i)
+      if (vox[i] != o.vox[i]) return vox[i] < o.vox[i];
+    return false;
+  }
+};
+struct Table {
+  size_t off = 0, bytes = 0;
+  int refs = 0;
+  bool uploaded = false;
+  void *d = nullptr, *twx = nullptr, *twy = nullptr;
+};
+
+struct Job {
+  uint64_t ticket = 0;
+  pd_request req{};
+  double t_submit = 0, t_start = 0, t_done = 0;
+  int slot = -1;
+  size_t off = 0;
+  Layout L{};
+  TableKey key{};
+  Table tab{};              // copy of the shared table's device pointers
+  int done_iters = 0;
+  bool finished = false;
+  pd_result res{};
+};
+
+struct GroupKey {
+  int nx, ny;
+  bool operator<(const GroupKey& o) const { return nx != o.nx ? nx < o.nx : ny < o.ny; }
+};
+
+}  // namespace
+
+struct pd_ctx {
+  pd_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int precision = PD_FP32;
+  int nslots = 0;
+
+  std::mutex mu;               // queues, tickets, arena, tables
+  std::condition_variable cv_work, cv_done;
+  std::mutex exec_mu;          // GPU submission (worker steps vs. pd_apply_kernel)
+  Arena arena;
+  std::map<TableKey, Table> tables;
+  std::deque<std::shared_ptr<Job>> queue;
+  std::vector<std::shared_ptr<Job>> active;
+  std::map<uint64_t, std::shared_ptr<Job>> jobs;
+  std::vector<int> free_slots;
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  pd_status poisoned = PD_OK;
+  std::thread worker;
+
+  // control arrays: device copies carved from the arena, pinned host mirrors.
+  // Entry nslots of vols/ctl/ranges is reserved for pd_apply_kernel.
+  size_t ctl_off = 0, ctl_bytes = 0;
+  Vol* d_vols = nullptr;       // nslots + 1
+  Ctl* d_ctl = nullptr;        // nslots + 1
+  int* d_slots = nullptr;      // nslots
+  Range* d_ranges = nullptr;   // nslots + 1
+  Vol* h_vols = nullptr;
+  Ctl* h_ctl = nullptr;
+  int* h_slots = nullptr;
+  Range* h_ranges = nullptr;
+
+  // kernel timing
+  bool time_kernels = false;
+  std::mutex tmu;
+  int64_t t_launches[2] = {0, 0};
+  double t_ms[2] = {0.0, 0.0};
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+bool hip_ok(pd_ctx* c, hipError_t e) {
+  if (e == hipSuccess) return true;
+  c->poisoned = PD_ERR_HIP;
+  return false;
+}
+
+// Acquire (or share) the table of a shape; caller holds c->mu.
+Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
+  auto it = c->tables.find(k);
+  if (it != c->tables.end()) {
+    it->second.refs++;
+    *fresh = false;
+    return &it->second;
+  }
+  Table t;
+  t.bytes = table_bytes(k.nx, k.ny, c->precision);
+  if (!c->arena.alloc(t.bytes, &t.off)) return nullptr;
+  size_t tsz = c->precision == PD_FP64 ? 8 : 4;
+  char* p = c->arena.ptr(t.off);
+  t.d = p;
+  t.twx = p + align_up((size_t)k.nx * k.ny * tsz);
+  t.twy = (char*)t.twx + align_up((size_t)k.nx * 2 * tsz);
+  t.refs = 1;
+  t.uploaded = false;
+  *fresh = true;
+  return &(c->tables[k] = t);
+}
+
+void release_table(pd_ctx* c, const TableKey& k) {
+  auto it = c->tables.find(k);
+  if (it == c->tables.end()) return;
+  if (--it->second.refs == 0) {
+    c->arena.release(it->second.off, it->second.bytes);
+    c->tables.erase(it);
+  }
+}
+
+template <typename T>
+hipError_t upload_table(pd_ctx* c, const TableKey& k, const Table& t) {
+  std::vector<double> D, re, im;
+  dipole_grid(k.nx, k.ny, k.b, k.vox, k.kernel, D);
+  std::vector<T> hd(D.size());
+  for (size_t i = 0; i < D.size(); ++i) hd[i] = (T)D[i];
+  hipError_t e = hipMemcpyAsync(t.d, hd.data(), hd.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  for (int axis = 0; axis < 2; ++axis) {
+    int n = axis == 0 ? k.nx : k.ny;
+    twiddles(n, re, im);
+    std::vector<T> tw(2 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+      tw[2 * m] = (T)re[m];
+      tw[2 * m + 1] = (T)im[m];
+    }
+    e = hipMemcpyAsync(axis == 0 ? t.twx : t.twy, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice,
+                       c->stream);
+    if (e != hipSuccess) return e;
+  }
+  // the host vectors die on return: wait for the copies
+  return hipStreamSynchronize(c->stream);
+}
+
+TableKey key_of(const pd_request& r) {
+  TableKey k{};
+  k.nx = r.nx;
+  k.ny = r.ny;
+  k.kernel = r.kernel;
+  if (r.kernel == PD_KERNEL_DIPOLE) {
+    unit_b0(r.b0, k.b);
+  } else {
+    k.b[0] = k.b[1] = k.b[2] = 0.0;
+  }
+  if (r.kernel == PD_KERNEL_DIPOLE) {
+    k.vox[0] = r.voxel[0];
+    k.vox[1] = r.voxel[1];
+  } else {
+    k.vox[0] = k.vox[1] = 0.0;
+  }
+  return k;
+}
+
+// Fill the kernel descriptor of a resident job (host mirror).
+void fill_vol(pd_ctx* c, const Job& j, Vol& V) {
+  std::memset(&V, 0, sizeof(V));
+  const Table& t = j.tab;
+  char* base = c->arena.ptr(j.off);
+  V.chi = base + j.L.off_chi;
+  V.yhat = base + j.L.off_yhat;
+  V.dhat = base + j.L.off_dhat;
+  V.ex = base + j.L.off_ex;
+  V.ex2 = base + j.L.off_ex2;
+  V.dtab = t.d;
+  V.twx = t.twx;
+  V.twy = t.twy;
+  V.part_row = (double*)(base + j.L.off_prow);
+  V.part_col = (double*)(base + j.L.off_pcol);
+  V.user_in = j.req.delta;
+  V.user_out = j.req.chi;
+  V.tau = j.req.tau;
+  V.sigma = j.req.sigma;
+  V.lam = j.req.lambda;
+  V.theta = j.req.theta;
+  V.gap_tol = j.req.gap_tol;
+  V.nx = j.req.nx;
+  V.ny = j.req.ny;
+  V.nz = j.req.nz;
+  V.P = j.L.P;
+  V.half_last = j.req.nz & 1;
+  V.max_iter = j.req.max_iter;
+  V.row_groups = j.L.row_groups;
+  V.col_groups = j.L.col_groups;
+  V.final_it = -1;
+}
+
+// Reserve arena + slot for a queued job; caller holds c->mu.  Returns false
+// if it does not fit now.
+bool reserve(pd_ctx* c, Job& j) {
+  if (c->free_slots.empty()) return false;
+  size_t off;
+  if (!c->arena.alloc(j.L.total, &off)) return false;
+  bool fresh = false;
+  Table* t = acquire_table(c, j.key, &fresh);
+  if (!t) {
+    c->arena.release(off, j.L.total);
+    return false;
+  }
+  (void)fresh;
+  j.off = off;
+  j.tab = *t;
+  j.slot = c->free_slots.back();
+  c->free_slots.pop_back();
+  return true;
+}
+
+void unreserve(pd_ctx* c, Job& j) {
+  c->arena.release(j.off, j.L.total);
+  release_table(c, j.key);
+  if (j.slot >= 0 && j.slot < c->nslots) c->free_slots.push_back(j.slot);
+  j.slot = -1;
+}
+
+hipEvent_t get_event(pd_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+// set-up of a newly admitted job: zero state, F delta, zero partials
+// ---------------------------------------------------------------------------
+hipError_t setup_job(pd_ctx* c, Job& j) {
+  Vol& V = c->h_vols[j.slot];
+  fill_vol(c, j, V);
+  hipError_t e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  char* base = c->arena.ptr(j.off);
+  if ((e = launch_zero(base, j.L.total, c->stream)) != hipSuccess) return e;
+  if ((e = launch_zero(c->d_ctl + j.slot, sizeof(Ctl), c->stream)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// Launch the transform set-up (F delta -> dhat) for the given jobs, whose Vol
+// entries are already on the device.
+hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
+  hipError_t e;
+  for (size_t k = 0; k < js.size(); ++k) c->h_ranges[k] = Range{js[k]->slot, 0};
+  if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, js.size() * sizeof(Range), hipMemcpyHostToDevice,
+                          c->stream)) != hipSuccess)
+    return e;
+  for (size_t k = 0; k < js.size(); ++k) {
+    Job* j = js[k];
+    const Range* rg = c->d_ranges + k;
+    int P = j->L.P;
+    // F_x of delta's rows -> ex, then F_y of ex's columns -> dhat
+    e = launch_row(j->req.nx, ROW_FWD_PLANAR, j->L.rows, P * j->L.row_groups, j->L.row_groups, c->d_vols, rg, 1,
+                   c->d_ctl, 0, c->precision, c->stream);
+    if (e != hipSuccess) return e;
+    e = launch_col(j->req.ny, COL_SETUP, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols, rg, 1,
+                   c->d_ctl, 0, c->precision, c->stream);
+    if (e != hipSuccess) return e;
+    // X'_0 = F_x chibar_0 = 0
+    e = launch_zero(c->arena.ptr(j->off) + j->L.off_ex, j->L.field, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  // the pinned range array is reused by the step: wait for the copy
+  return hipStreamSynchronize(c->stream);
+}
+
+// One scheduling step over all resident jobs.  Returns HIP status.
+hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
+  bool any_gap = false;
+  for (auto& j : act) any_gap |= j->req.gap_tol > 0;
+  int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : (any_gap ? 10 : 50);
+  K = std::min(K, kMaxStep);
+
+  // group resident jobs by slice shape; build descriptors and range tables
+  std::map<GroupKey, std::vector<Job*>> groups;
+  for (auto& j : act) groups[GroupKey{j->req.nx, j->req.ny}].push_back(j.get());
+  hipError_t e;
+  struct Launch {
+    int nx, ny, rows, cols, rg, cg;
+    int range_off, nranges, npairs;
+  };
+  std::vector<Launch> launches;
+  int k = 0;
+  int nslot_list = 0;
+  uint64_t any_check = 0;
+  for (auto& g : groups) {
+    Launch L{};
+    L.nx = g.first.nx;
+    L.ny = g.first.ny;
+    L.range_off = k;
+    for (Job* j : g.second) {
+      L.rows = j->L.rows;
+      L.cols = j->L.cols;
+      L.rg = j->L.row_groups;
+      L.cg = j->L.col_groups;
+      c->h_ranges[k++] = Range{j->slot, L.npairs};   // first pair; scaled per kernel below
+      L.npairs += j->L.P;
+      Vol& V = c->h_vols[j->slot];
+      fill_vol(c, *j, V);
+      int rem = j->req.max_iter - j->done_iters;
+      V.iters = std::min(K, rem);
+      V.done_base = j->done_iters;
+      V.final_it = (rem <= K) ? rem - 1 : -1;
+      V.check_mask = 0;
+      for (int it = 0; it < V.iters; ++it) {
+        int n = j->done_iters + it + 1;
+        if ((j->req.gap_tol > 0 && n % j->req.check_every == 0) || n == j->req.max_iter)
+          V.check_mask |= (1ull << it);
+      }
+      if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
+        V.iters = 1;
+        V.done_base = -1;
+        V.final_it = 0;
+        V.check_mask = 1;
+        V.check_only = 1;
+      }
+      any_check |= V.check_mask;
+      c->h_slots[nslot_list++] = j->slot;
+    }
+    L.nranges = k - L.range_off;
+    launches.push_back(L);
+  }
+  // Range.first counts pairs; the column and row kernels need it in
+  // workgroups, so keep one table per kernel kind: [0, k) rows, [k, 2k) cols.
+  for (int i = 0; i < k; ++i) c->h_ranges[k + i] = c->h_ranges[i];
+  for (auto& L : launches)
+    for (int i = 0; i < L.nranges; ++i) {
+      c->h_ranges[L.range_off + i].first *= L.rg;
+      c->h_ranges[k + L.range_off + i].first *= L.cg;
+    }
+  if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, sizeof(Range) * 2 * k, hipMemcpyHostToDevice, c->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * c->nslots, hipMemcpyHostToDevice, c->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(c->d_slots, c->h_slots, sizeof(int) * nslot_list, hipMemcpyHostToDevice,
+                          c->stream)) != hipSuccess)
+    return e;
+
+  int kmax = 0;
+  for (auto& j : act) kmax = std::max(kmax, c->h_vols[j->slot].iters);
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
+  for (int it = 0; it < kmax; ++it) {
+    for (auto& L : launches) {
+      const Range* rrow = c->d_ranges + L.range_off;
+      const Range* rcol = c->d_ranges + k + L.range_off;
+      for (int kind = 0; kind < 2; ++kind) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (c->time_kernels) {
+          e0 = get_event(c);
+          e1 = get_event(c);
+          if (e0) (void)hipEventRecord(e0, c->stream);
+        }
+        if (kind == 0)
+          e = launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
+                         c->precision, c->stream);
+        else
+          e = launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl, it,
+                         c->precision, c->stream);
+        if (e != hipSuccess) return e;
+        if (c->time_kernels && e0 && e1) {
+          (void)hipEventRecord(e1, c->stream);
+          evs.push_back({kind, {e0, e1}});
+        }
+      }
+    }
+    if ((any_check >> it) & 1ull) {
+      for (auto& L : launches) {
+        const Range* rcol = c->d_ranges + k + L.range_off;
+        e = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
+                       c->precision, c->stream);
+        if (e != hipSuccess) return e;
+      }
+      e = launch_reduce(nslot_list, c->d_vols, c->d_slots, c->d_ctl, it, c->precision, c->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  if ((e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl) * c->nslots, hipMemcpyDeviceToHost, c->stream)) !=
+      hipSuccess)
+    return e;
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
+  if (!evs.empty()) {
+    std::lock_guard<std::mutex> lk(c->tmu);
+    for (auto& x : evs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+        c->t_launches[x.first]++;
+        c->t_ms[x.first] += ms;
+      }
+      c->ev_pool.push_back(x.second.first);
+      c->ev_pool.push_back(x.second.second);
+    }
+  }
+  return hipSuccess;
+}
+
+void finish_job(pd_ctx* c, Job& j, pd_status st) {
+  j.res.status = st;
+  j.res.t_submit = j.t_submit;
+  j.res.t_start = j.t_start;
+  j.res.t_done = now_s();
+  j.finished = true;
+}
+
+void worker_main(pd_ctx* c) {
+  (void)hipSetDevice(c->device);
+  std::unique_lock<std::mutex> lk(c->mu);
+  while (true) {
+    c->cv_work.wait(lk, [&] { return c->stopping || !c->queue.empty() || !c->active.empty(); });
+    if (c->stopping) break;
+    if (c->poisoned != PD_OK) {
+      for (auto& j : c->queue) finish_job(c, *j, c->poisoned);
+      for (auto& j : c->active) finish_job(c, *j, c->poisoned);
+      c->queue.clear();
+      c->active.clear();
+      c->cv_done.notify_all();
+      continue;
+    }
+    // admission, FIFO
+    std::vector<std::shared_ptr<Job>> admitted;
+    while (!c->queue.empty()) {
+      auto j = c->queue.front();
+      if (!reserve(c, *j)) break;
+      c->queue.pop_front();
+      admitted.push_back(j);
+    }
+    std::vector<std::pair<TableKey, Table>> uploads;
+    for (auto& j : admitted) {
+      Table& t = c->tables.at(j->key);
+      if (!t.uploaded) {
+        t.uploaded = true;
+        uploads.push_back({j->key, t});
+      }
+    }
+    lk.unlock();
+
+    bool ok = true;
+    {
+      std::lock_guard<std::mutex> ex(c->exec_mu);
+      for (auto& u : uploads) {
+        hipError_t e = c->precision == PD_FP64 ? upload_table<double>(c, u.first, u.second)
+                                               : upload_table<float>(c, u.first, u.second);
+        if (!hip_ok(c, e)) ok = false;
+      }
+      std::vector<Job*> js;
+      for (auto& j : admitted) {
+        j->t_start = now_s();
+        if (ok && !hip_ok(c, setup_job(c, *j))) ok = false;
+        js.push_back(j.get());
+      }
+      if (ok && !js.empty() && !hip_ok(c, launch_setup(c, js))) ok = false;
+    }
+    lk.lock();
+    for (auto& j : admitted) c->active.push_back(j);
+    if (!ok) continue;   // poisoned: next loop turn fails everything
+    if (c->active.empty()) continue;
+    std::vector<std::shared_ptr<Job>> act = c->active;
+    lk.unlock();
+
+    hipError_t e;
+    std::vector<std::shared_ptr<Job>> retired;
+    {
+      std::lock_guard<std::mutex> ex(c->exec_mu);
+      e = run_step(c, act);
+      if (e == hipSuccess) {
+        for (auto& j : act) {
+          const Ctl& C = c->h_ctl[j->slot];
+          Vol& V = c->h_vols[j->slot];
+          // the final check always stops a volume; the cap test only guards
+          // against a step that could not run it
+          if (C.stop || (j->req.max_iter > 0 && j->done_iters + V.iters >= j->req.max_iter)) {
+            j->res.iterations = C.stop ? C.stop_iter : j->done_iters + V.iters;
+            j->res.primal = C.primal;
+            j->res.dual = C.dual;
+            j->res.rel_gap = C.rel_gap;
+            j->done_iters = j->res.iterations;
+            retired.push_back(j);
+            if (j->req.max_iter == 0) {
+              e = hipMemsetAsync(j->req.chi, 0,
+                                 (size_t)j->req.nx * j->req.ny * j->req.nz * (c->precision == PD_FP64 ? 8 : 4),
+                                 c->stream);
+            } else {
+              e = launch_store_chi(c->d_vols, j->slot, (size_t)j->L.P * j->req.nx * j->req.ny, c->precision,
+                                   c->stream);
+            }
+            if (e != hipSuccess) break;
+          } else {
+            j->done_iters += V.iters;
+          }
+        }
+        if (e == hipSuccess && !retired.empty()) e = hipStreamSynchronize(c->stream);
+      }
+    }
+    lk.lock();
+    if (!hip_ok(c, e)) continue;
+    for (auto& j : retired) {
+      const Ctl& C = c->h_ctl[j->slot];
+      finish_job(c, *j, C.status ? PD_ERR_NONFINITE : PD_OK);
+      unreserve(c, *j);
+      c->active.erase(std::find(c->active.begin(), c->active.end(), j));
+    }
+    if (!retired.empty()) c->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* pd_status_string(pd_status s) {
+  switch (s) {
+    case PD_OK: return "ok";
+    case PD_PENDING: return "pending";
+    case PD_ERR_ARG: return "invalid argument";
+    case PD_ERR_SIZE: return "unsupported size";
+    case PD_ERR_STEP: return "step sizes violate tau*sigma*max|D|^2 < 1 or theta outside [0,1]";
+    case PD_ERR_BUDGET: return "request larger than the arena";
+    case PD_ERR_NONFINITE: return "non-finite duality gap";
+    case PD_ERR_HIP: return "HIP runtime error";
+    case PD_ERR_CANCELLED: return "cancelled";
+    case PD_ERR_TICKET: return "unknown ticket";
+    case PD_ERR_NODEVICE: return "no usable GPU";
+    default: return "unknown status";
+  }
+}
+
+double pd_now(void) { return now_s(); }
+
+pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes) {
+  pd_status s = validate(r, precision, nullptr);
+  if (s != PD_OK) return s;
+  if (state_bytes) *state_bytes = layout_of(*r, precision).total + table_bytes(r->nx, r->ny, precision);
+  return PD_OK;
+}
+
+pd_status pd_kernel_norm(const pd_request* r, double* norm) {
+  if (!r || !norm) return PD_ERR_ARG;
+  if (!size_supported(r->nx) || !size_supported(r->ny)) return PD_ERR_SIZE;
+  double bu[3];
+  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
+  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
+  std::vector<double> D;
+  dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
+  *norm = grid_norm(D);
+  return PD_OK;
+}
+
+pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
+  if (!cfg || !out) return PD_ERR_ARG;
+  *out = nullptr;
+  if (cfg->precision != PD_FP32 && cfg->precision != PD_FP64) return PD_ERR_ARG;
+  if (!cfg->arena || cfg->arena_bytes == 0 || ((uintptr_t)cfg->arena & (kAlign - 1)) != 0) return PD_ERR_ARG;
+  if (cfg->max_slots < 0 || cfg->step_iters < 0 || cfg->step_iters > kMaxStep) return PD_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PD_ERR_NODEVICE;
+  if (cfg->device < 0 || cfg->device >= ndev) return PD_ERR_ARG;
+  if (hipSetDevice(cfg->device) != hipSuccess) return PD_ERR_HIP;
+
+  std::unique_ptr<pd_ctx> c(new pd_ctx());
+  c->cfg = *cfg;
+  c->device = cfg->device;
+  c->precision = cfg->precision;
+  c->nslots = cfg->max_slots > 0 ? cfg->max_slots : kDefaultSlots;
+  c->time_kernels = (cfg->flags & PD_FLAG_TIME_KERNELS) != 0;
+  c->arena.init((char*)cfg->arena, cfg->arena_bytes);
+
+  c->ctl_bytes = align_up(sizeof(Vol) * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
+                 align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * (2 * c->nslots + 1));
+  if (!c->arena.alloc(c->ctl_bytes, &c->ctl_off)) return PD_ERR_BUDGET;
+  char* p = c->arena.ptr(c->ctl_off);
+  c->d_vols = (Vol*)p;
+  p += align_up(sizeof(Vol) * (c->nslots + 1));
+  c->d_ctl = (Ctl*)p;
+  p += align_up(sizeof(Ctl) * (c->nslots + 1));
+  c->d_slots = (int*)p;
+  p += align_up(sizeof(int) * c->nslots);
+  c->d_ranges = (Range*)p;
+
+  if (cfg->stream) {
+    c->stream = (hipStream_t)cfg->stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return PD_ERR_HIP;
+    c->own_stream = true;
+  }
+  if (hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_slots, sizeof(int) * c->nslots, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * (2 * c->nslots + 1), hipHostMallocDefault) !=
+          hipSuccess) {
+    if (c->h_vols) (void)hipHostFree(c->h_vols);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->h_slots) (void)hipHostFree(c->h_slots);
+    if (c->h_ranges) (void)hipHostFree(c->h_ranges);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    return PD_ERR_HIP;
+  }
+  std::memset(c->h_vols, 0, sizeof(Vol) * (c->nslots + 1));
+  std::memset(c->h_ctl, 0, sizeof(Ctl) * (c->nslots + 1));
+  for (int s = c->nslots - 1; s >= 0; --s) c->free_slots.push_back(s);
+  // all descriptors start idle (iters = 0)
+  if (hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * (c->nslots + 1), hipMemcpyHostToDevice, c->stream) !=
+          hipSuccess ||
+      launch_zero(c->d_ctl, sizeof(Ctl) * (c->nslots + 1), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipHostFree(c->h_vols);
+    (void)hipHostFree(c->h_ctl);
+    (void)hipHostFree(c->h_slots);
+    (void)hipHostFree(c->h_ranges);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    return PD_ERR_HIP;
+  }
+  pd_ctx* raw = c.release();
+  raw->worker = std::thread(worker_main, raw);
+  *out = raw;
+  return PD_OK;
+}
+
+pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* tickets) {
+  if (!c || (n > 0 && (!r || !tickets)) || n < 0) return PD_ERR_ARG;
+  std::vector<std::shared_ptr<Job>> js;
+  size_t avail = c->arena.size() - align_up(c->ctl_bytes);
+  for (int i = 0; i < n; ++i) {
+    pd_status s = validate(&r[i], c->precision, nullptr);
+    if (s != PD_OK) return s;
+    auto j = std::make_shared<Job>();
+    j->req = r[i];
+    j->L = layout_of(r[i], c->precision);
+    j->key = key_of(r[i]);
+    // the request and its table must fit in an otherwise empty arena
+    size_t need = j->L.total + table_bytes(r[i].nx, r[i].ny, c->precision);
+    if (need > avail) return PD_ERR_BUDGET;
+    js.push_back(j);
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->poisoned != PD_OK) return c->poisoned;
+  double t = now_s();
+  for (int i = 0; i < n; ++i) {
+    js[i]->ticket = c->next_ticket++;
+    js[i]->t_submit = t;
+    tickets[i] = js[i]->ticket;
+    c->jobs[js[i]->ticket] = js[i];
+    c->queue.push_back(js[i]);
+  }
+  c->cv_work.notify_all();
+  return PD_OK;
+}
+
+pd_status pd_poll(pd_ctx* c, uint64_t ticket, pd_result* out, int timeout_ms) {
+  if (!c) return PD_ERR_ARG;
+  std::unique_lock<std::mutex> lk(c->mu);
+  auto it = c->jobs.find(ticket);
+  if (it == c->jobs.end()) return PD_ERR_TICKET;
+  std::shared_ptr<Job> j = it->second;
+  auto done = [&] { return j->finished; };
+  if (timeout_ms < 0)
+    c->cv_done.wait(lk, done);
+  else if (timeout_ms > 0)
+    c->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done);
+  if (!j->finished) return PD_PENDING;
+  if (out) *out = j->res;
+  c->jobs.erase(ticket);
+  return j->res.status;
+}
+
+pd_status pd_destroy(pd_ctx* c) {
+  if (!c) return PD_OK;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->stopping = true;
+    c->cv_work.notify_all();
+  }
+  if (c->worker.joinable()) c->worker.join();
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto& j : c->queue) finish_job(c, *j, PD_ERR_CANCELLED);
+    for (auto& j : c->active) finish_job(c, *j, PD_ERR_CANCELLED);
+    c->cv_done.notify_all();
+  }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->h_vols) (void)hipHostFree(c->h_vols);
+  if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+  if (c->h_slots) (void)hipHostFree(c->h_slots);
+  if (c->h_ranges) (void)hipHostFree(c->h_ranges);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return PD_OK;
+}
+
+pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
+  if (!c || !r) return PD_ERR_ARG;
+  if (!size_supported(r->nx) || !size_supported(r->ny) || r->nz < 1) return PD_ERR_SIZE;
+  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
+  double bu[3];
+  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
+  if (!isfin(r->voxel[0]) || !isfin(r->voxel[1]) || r->voxel[0] <= 0 || r->voxel[1] <= 0) return PD_ERR_ARG;
+  if (!r->delta || !r->chi || r->delta == r->chi) return PD_ERR_ARG;
+
+  // Only the exchange buffer is used: every state pointer of the descriptor
+  // aliases it.
+  Job j;
+  j.req = *r;
+  j.req.gap_tol = 0.0;
+  j.L = layout_of(j.req, c->precision);
+  j.L.off_chi = j.L.off_yhat = j.L.off_dhat = j.L.off_ex = j.L.off_ex2 = 0;
+  j.L.off_prow = j.L.off_pcol = 0;
+  j.L.total = j.L.field;
+  j.key = key_of(j.req);
+  bool fresh = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned != PD_OK) return c->poisoned;
+    size_t off;
+    if (!c->arena.alloc(j.L.total, &off)) return PD_ERR_BUDGET;
+    Table* t = acquire_table(c, j.key, &fresh);
+    if (!t) {
+      c->arena.release(off, j.L.total);
+      return PD_ERR_BUDGET;
+    }
+    if (fresh) t->uploaded = true;   // uploaded below, before any use
+    j.tab = *t;
+    j.off = off;
+    j.slot = c->nslots;              // the reserved descriptor slot
+  }
+  hipError_t e = hipSuccess;
+  {
+    std::lock_guard<std::mutex> ex(c->exec_mu);
+    (void)hipSetDevice(c->device);
+    if (fresh)
+      e = c->precision == PD_FP64 ? upload_table<double>(c, j.key, j.tab) : upload_table<float>(c, j.key, j.tab);
+    Vol& V = c->h_vols[j.slot];
+    fill_vol(c, j, V);
+    Range* hr = c->h_ranges + 2 * c->nslots;
+    *hr = Range{j.slot, 0};
+    const Range* dr = c->d_ranges + 2 * c->nslots;
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
+    const int P = j.L.P;
+    if (e == hipSuccess)
+      e = launch_row(r->nx, ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr, 1,
+                     c->d_ctl, 0, c->precision, c->stream);
+    if (e == hipSuccess)
+      e = launch_col(r->ny, COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1, c->d_ctl,
+                     0, c->precision, c->stream);
+    if (e == hipSuccess)
+      e = launch_row(r->nx, ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr, 1,
+                     c->d_ctl, 0, c->precision, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = e2;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->arena.release(j.off, j.L.total);
+  release_table(c, j.key);
+  if (e != hipSuccess) {
+    c->poisoned = PD_ERR_HIP;
+    return PD_ERR_HIP;
+  }
+  return PD_OK;
+}
+
+pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms) {
+  if (!c || kind < 0 || kind > 1) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->tmu);
+  if (launches) *launches = c->t_launches[kind];
+  if (total_ms) *total_ms = c->t_ms[kind];
+  return PD_OK;
+}
+
+pd_status pd_kernel_time_reset(pd_ctx* c) {
+  if (!c) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->tmu);
+  c->t_launches[0] = c->t_launches[1] = 0;
+  c->t_ms[0] = c->t_ms[1] = 0.0;
+  return PD_OK;
+}
+
+pd_status pd_arena_usage(pd_ctx* c, size_t* used, int* resident, int* queued) {
+  if (!c) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (used) *used = c->arena.used();
+  if (resident) *resident = (int)c->active.size();
+  if (queued) *queued = (int)c->queue.size();
+  return PD_OK;
+}
+
+}  // extern "C"

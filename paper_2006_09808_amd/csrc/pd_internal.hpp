@@ -1,0 +1,97 @@
+// pd_internal.hpp - structures shared by the host scheduler and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdk {
+
+// One resident request (a volume of nz slices), as the kernels see it.
+// Slices 2p and 2p+1 of the volume share one complex field ("pair" p):
+// slice 2p is the real part, slice 2p+1 the imaginary part.  D is real and
+// even, so A acts on the two parts independently.  All state buffers are
+// [P][ny][nx] complex, x fastest.
+struct Vol {
+  void* chi;          // chi_n, pair-interleaved
+  void* yhat;         // dual variable, kept in the frequency domain
+  void* dhat;         // F(delta), computed once at admission
+  void* ex;           // exchange buffer between the column and row kernels
+  void* ex2;          // row transform of chi on check iterations (may alias ex)
+  const void* dtab;   // D[ky][kx], real, shared by volumes of one kernel shape
+  const void* twx;    // exp(-2 pi i m / nx), m < nx
+  const void* twy;    // exp(-2 pi i m / ny), m < ny
+  double* part_row;   // per row-kernel workgroup: sum|chi|, max|A y|
+  double* part_col;   // per check-kernel workgroup: sum|D F chi - F delta|^2,
+                      //   sum |yhat|^2, Re sum yhat conj(dhat)
+  const void* user_in;   // planar [nz][ny][nx] input (field map / operator input)
+  void* user_out;        // planar [nz][ny][nx] output
+  double tau, sigma, lam, theta;
+  double gap_tol;
+  int nx, ny, nz, P;
+  int half_last;      // nz odd: the last pair's imaginary part is padding
+  int iters;          // iterations to run in this step (0: idle)
+  int done_base;      // iterations completed before this step
+  int max_iter;
+  int final_it;       // step iteration of the volume's last update, or -1
+  int row_groups;     // row-kernel workgroups per pair
+  int col_groups;     // column-kernel workgroups per pair
+  int check_only;     // max_iter == 0: only the gap of chi_0 = 0 is evaluated
+  uint64_t check_mask;  // bit `it`: gap partials after step iteration `it`
+};
+
+// Device-side control/result block of one resident request.
+struct Ctl {
+  int stop;           // set by the gap reduction; kernels skip stopped volumes
+  int stop_iter;      // iterations applied when the last check ran
+  int status;         // 0 ok, 1 non-finite
+  int checks;
+  double primal, dual, rel_gap, max_ay;
+};
+
+// One volume's share of a launch: workgroups [first, next range's first)
+// belong to volume `slot`, `groups` consecutive workgroups per pair.
+struct Range {
+  int slot;
+  int first;
+};
+
+// Workgroup -> (slot, pair, group) by binary search over the launch's ranges.
+__device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int nranges, int groups,
+                                          int& slot, int& pair, int& g) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = nranges - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (ranges[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  slot = ranges[lo].slot;
+  int local = b - ranges[lo].first;
+  pair = local / groups;
+  g = local - pair * groups;
+}
+
+enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3 };
+enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2 };
+
+constexpr int kThreads = 256;
+
+// Launchers, one set per transform length (defined in pd_kern_<N>.hip).
+// `cols` is the strip width / `rows` the rows per workgroup, `grid` the number
+// of workgroups and `groups` the workgroups per pair.
+
+bool size_supported(int n);
+int col_strip(int ny, int nx);   // columns per column-kernel workgroup
+int row_group(int nx, int ny);   // rows per row-kernel workgroup
+
+hipError_t launch_col(int n, int mode, int cols, int grid, int groups, const Vol* vols,
+                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st);
+hipError_t launch_row(int n, int mode, int rows, int grid, int groups, const Vol* vols,
+                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st);
+hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl, int it,
+                         int precision, hipStream_t st);
+hipError_t launch_store_chi(const Vol* vols, int slot, size_t npairs_pts, int precision,
+                            hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace pdk

@@ -1,0 +1,399 @@
+// pd_kern_impl.hpp - the two kernels of one primal-dual iteration and their
+// set-up / check variants, templated on precision and transform length.
+// Included by one pd_kern_<N>.hip translation unit per transform length.
+//
+// One iteration of the PD pseudocode (Sec. II-A) on a slice pair z = a + i b
+// runs as two launches, with the dual kept in the frequency domain:
+//
+//  column kernel (length ny transforms over column strips):
+//     Xhat = F_y X'                       X' = row transform of chibar_n
+//     Yhat <- (Yhat + sigma (D Xhat - F delta)) / (1 + sigma)     dual prox
+//     X'   <- F_y^-1 (D Yhat / (nx ny))                          (A y, column half)
+//  row kernel (length nx transforms over rows):
+//     u      = F_x^-1 X'                  u = A y_{n+1}
+//     chi'   = soft(chi - tau u, tau lam) primal prox
+//     chibar = chi' + theta (chi' - chi)  over-relaxation
+//     X'     = F_x chibar                 row half of the next forward FFT
+//
+// Because F is linear and D is real, F y_n equals the frequency-domain dual
+// by induction from y_0 = 0, so each iteration needs one forward and one
+// inverse 2-D FFT instead of the image-domain form's two of each.
+#pragma once
+
+#include "pd_fft.hpp"
+#include "pd_internal.hpp"
+
+namespace pdk {
+
+template <typename T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Block-wide reduction of NV doubles (sum, or max for entries with MAXMASK
+// bit set); fixed tree, so the result is deterministic.  Result valid in
+// thread 0.  Uses its own LDS.
+template <int NV, int MAXMASK>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], int tid) {
+  __shared__ double red[NV][kThreads / 64];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      double o = __shfl_down(x, off, 64);
+      x = ((MAXMASK >> i) & 1) ? fmax(x, o) : x + o;
+    }
+    if ((tid & 63) == 0) red[i][tid >> 6] = x;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double x = red[i][0];
+#pragma unroll
+      for (int w = 1; w < kThreads / 64; ++w) x = ((MAXMASK >> i) & 1) ? fmax(x, red[i][w]) : x + red[i][w];
+      v[i] = x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Column kernel: strips of S columns, transforms of length NY.
+// ---------------------------------------------------------------------------
+template <typename T, int NY, int S, int MODE>
+__global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
+                                                  const Range* __restrict__ ranges, int nranges,
+                                                  Ctl* __restrict__ ctl, int groups, int it) {
+  using F = Fft<T, NY, S, kThreads, true>;
+  constexpr int QA = F::template QF<-1>();  // forward first radix == inverse last radix
+  constexpr int QB = F::template QL<-1>();  // forward last radix == inverse first radix
+  __shared__ cpx<T> lds[F::LDS_ELEMS];
+
+  const int tid = threadIdx.x;
+  int slot, pair, g;
+  find_work(ranges, nranges, groups, slot, pair, g);
+  const Vol& V = vols[slot];
+  if constexpr (MODE == COL_ITER) {
+    if (ctl[slot].stop || it >= V.iters || V.check_only) return;
+  } else if constexpr (MODE == COL_CHECK) {
+    if (ctl[slot].stop || it >= V.iters || !((V.check_mask >> it) & 1ull)) return;
+  }
+  const int nx = V.nx;
+  const int c0 = g * S;
+  const size_t base = (size_t)pair * (size_t)nx * NY;
+  const cpx<T>* __restrict__ tw = (const cpx<T>*)V.twy;
+  const cpx<T>* __restrict__ src =
+      (const cpx<T>*)(MODE == COL_CHECK ? V.ex2 : V.ex) + base + c0;
+
+  cpx<T> a[F::template nq<QA>()][QA];
+  cpx<T> b[F::template nq<QB>()][QB];
+#pragma unroll
+  for (int q = 0; q < F::template nq<QA>(); ++q)
+#pragma unroll
+    for (int r = 0; r < QA; ++r) {
+      int s, n;
+      if (F::template pos<QA>(tid, q, r, s, n)) a[q][r] = src[(size_t)n * nx + s];
+    }
+  F::template run<-1>(a, b, lds, tw, tid);
+
+  const T* __restrict__ dtab = (const T*)V.dtab + c0;
+  if constexpr (MODE == COL_SETUP) {
+    cpx<T>* dh = (cpx<T>*)V.dhat + base + c0;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QB; ++r) {
+        int s, n;
+        if (F::template pos<QB>(tid, q, r, s, n)) dh[(size_t)n * nx + s] = b[q][r];
+      }
+    return;
+  } else if constexpr (MODE == COL_CHECK) {
+    const cpx<T>* __restrict__ dh = (const cpx<T>*)V.dhat + base + c0;
+    const cpx<T>* __restrict__ yh = (const cpx<T>*)V.yhat + base + c0;
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QB; ++r) {
+        int s, n;
+        if (F::template pos<QB>(tid, q, r, s, n)) {
+          size_t o = (size_t)n * nx + s;
+          T d = dtab[(size_t)n * nx + s];
+          cpx<T> e = dh[o], y = yh[o];
+          double rx = (double)(d * b[q][r].x - e.x), ry = (double)(d * b[q][r].y - e.y);
+          acc[0] += rx * rx + ry * ry;
+          acc[1] += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+          acc[2] += (double)y.x * (double)e.x + (double)y.y * (double)e.y;
+        }
+      }
+    block_reduce<3, 0>(acc, tid);
+    if (tid == 0) {
+      double* out = V.part_col + ((size_t)pair * groups + g) * 3;
+      out[0] = acc[0];
+      out[1] = acc[1];
+      out[2] = acc[2];
+    }
+    return;
+  } else {
+    const T invN = (T)(1.0 / ((double)nx * (double)NY));
+    if constexpr (MODE == COL_ITER) {
+      const T sig = (T)V.sigma;
+      const T inv1ps = (T)(1.0 / (1.0 + V.sigma));
+      cpx<T>* __restrict__ yh = (cpx<T>*)V.yhat + base + c0;
+      const cpx<T>* __restrict__ dh = (const cpx<T>*)V.dhat + base + c0;
+#pragma unroll
+      for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+          int s, n;
+          if (F::template pos<QB>(tid, q, r, s, n)) {
+            size_t o = (size_t)n * nx + s;
+            T d = dtab[o];
+            cpx<T> y = yh[o], e = dh[o];
+            cpx<T> yn = mk((y.x + sig * (d * b[q][r].x - e.x)) * inv1ps,
+                           (y.y + sig * (d * b[q][r].y - e.y)) * inv1ps);
+            yh[o] = yn;
+            T dn = d * invN;
+            b[q][r] = mk(dn * yn.x, dn * yn.y);
+          }
+        }
+    } else {  // COL_APPLY: multiply by D / (nx ny)
+#pragma unroll
+      for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QB; ++r) {
+          int s, n;
+          if (F::template pos<QB>(tid, q, r, s, n)) {
+            T dn = dtab[(size_t)n * nx + s] * invN;
+            b[q][r] = mk(dn * b[q][r].x, dn * b[q][r].y);
+          }
+        }
+    }
+    F::sync_before_reuse();
+    F::template run<+1>(b, a, lds, tw, tid);
+    cpx<T>* dst = (cpx<T>*)V.ex + base + c0;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QA>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QA; ++r) {
+        int s, n;
+        if (F::template pos<QA>(tid, q, r, s, n)) dst[(size_t)n * nx + s] = a[q][r];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row kernel: S rows per workgroup, transforms of length NX.
+// ---------------------------------------------------------------------------
+template <typename T, int NX, int S, int MODE>
+__global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
+                                                  const Range* __restrict__ ranges, int nranges,
+                                                  Ctl* __restrict__ ctl, int groups, int it) {
+  using F = Fft<T, NX, S, kThreads, false>;
+  constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
+  constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
+  __shared__ cpx<T> lds[F::LDS_ELEMS];
+
+  const int tid = threadIdx.x;
+  int slot, pair, g;
+  find_work(ranges, nranges, groups, slot, pair, g);
+  const Vol& V = vols[slot];
+  if constexpr (MODE == ROW_ITER) {
+    if (ctl[slot].stop || it >= V.iters || V.check_only) return;
+  }
+  const int ny = V.ny;
+  const int r0 = g * S;
+  const size_t base = (size_t)pair * (size_t)NX * ny + (size_t)r0 * NX;
+  const cpx<T>* __restrict__ tw = (const cpx<T>*)V.twx;
+  const bool pad_imag = V.half_last && pair == V.P - 1;
+  const size_t plane = (size_t)NX * ny;
+
+  cpx<T> a[F::template nq<QI>()][QI];
+  cpx<T> b[F::template nq<QO>()][QO];
+
+  if constexpr (MODE == ROW_FWD_PLANAR) {
+    const T* __restrict__ in = (const T*)V.user_in + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QO; ++r) {
+        int s, n;
+        if (F::template pos<QO>(tid, q, r, s, n)) {
+          size_t o = (size_t)s * NX + n;
+          b[q][r] = mk(in[o], pad_imag ? (T)0 : in[plane + o]);
+        }
+      }
+    F::template run<-1>(b, a, lds, tw, tid);
+    cpx<T>* dst = (cpx<T>*)V.ex + base;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QI; ++r) {
+        int s, n;
+        if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+      }
+    return;
+  } else {
+    const cpx<T>* __restrict__ src = (const cpx<T>*)V.ex + base;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QI; ++r) {
+        int s, n;
+        if (F::template pos<QI>(tid, q, r, s, n)) a[q][r] = src[(size_t)s * NX + n];
+      }
+    F::template run<+1>(a, b, lds, tw, tid);
+
+    if constexpr (MODE == ROW_INV_PLANAR) {
+      T* __restrict__ out = (T*)V.user_out + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+#pragma unroll
+      for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QO; ++r) {
+          int s, n;
+          if (F::template pos<QO>(tid, q, r, s, n)) {
+            size_t o = (size_t)s * NX + n;
+            out[o] = b[q][r].x;
+            if (!pad_imag) out[plane + o] = b[q][r].y;
+          }
+        }
+      return;
+    } else {  // ROW_ITER
+      const T tau = (T)V.tau;
+      const T tl = (T)(V.tau * V.lam);
+      const T theta = (T)V.theta;
+      const bool check = (V.check_mask >> it) & 1ull;
+      const bool last = (it == V.final_it);
+      cpx<T>* __restrict__ chi = (cpx<T>*)V.chi + base;
+      cpx<T> c[F::template nq<QO>()][QO];
+      double acc[2] = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QO; ++r) {
+          int s, n;
+          if (F::template pos<QO>(tid, q, r, s, n)) {
+            size_t o = (size_t)s * NX + n;
+            cpx<T> x0 = chi[o];
+            cpx<T> u = b[q][r];
+            T vx = x0.x - tau * u.x, vy = x0.y - tau * u.y;
+            T nx_ = vx - clampv(vx, -tl, tl);
+            T ny_ = vy - clampv(vy, -tl, tl);
+            if (pad_imag) {
+              ny_ = (T)0;
+              u.y = (T)0;
+            }
+            cpx<T> xn = mk(nx_, ny_);
+            chi[o] = xn;
+            c[q][r] = xn;
+            b[q][r] = mk(nx_ + theta * (nx_ - x0.x), ny_ + theta * (ny_ - x0.y));
+            if (check) {
+              acc[0] += fabs((double)nx_) + fabs((double)ny_);
+              acc[1] = fmax(acc[1], fmax(fabs((double)u.x), fabs((double)u.y)));
+            }
+          }
+        }
+      if (check) {
+        block_reduce<2, 2>(acc, tid);
+        if (tid == 0) {
+          double* out = V.part_row + ((size_t)pair * groups + g) * 2;
+          out[0] = acc[0];
+          out[1] = acc[1];
+        }
+      }
+      if (!last) {
+        F::sync_before_reuse();
+        F::template run<-1>(b, a, lds, tw, tid);
+        cpx<T>* dst = (cpx<T>*)V.ex + base;
+#pragma unroll
+        for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+          for (int r = 0; r < QI; ++r) {
+            int s, n;
+            if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+          }
+      }
+      if (check) {
+        F::sync_before_reuse();
+        F::template run<-1>(c, a, lds, tw, tid);
+        cpx<T>* dst = (cpx<T>*)V.ex2 + base;
+#pragma unroll
+        for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+          for (int r = 0; r < QI; ++r) {
+            int s, n;
+            if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+          }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-length launchers
+// ---------------------------------------------------------------------------
+template <int N, typename T, int S>
+hipError_t launch_col_t(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                        int it, hipStream_t st) {
+  dim3 gr(grid), bl(kThreads);
+  switch (mode) {
+    case COL_ITER: hipLaunchKernelGGL((k_col<T, N, S, COL_ITER>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_CHECK: hipLaunchKernelGGL((k_col<T, N, S, COL_CHECK>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_SETUP: hipLaunchKernelGGL((k_col<T, N, S, COL_SETUP>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_APPLY: hipLaunchKernelGGL((k_col<T, N, S, COL_APPLY>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int N, typename T, int S>
+hipError_t launch_row_t(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                        int it, hipStream_t st) {
+  dim3 gr(grid), bl(kThreads);
+  switch (mode) {
+    case ROW_ITER: hipLaunchKernelGGL((k_row<T, N, S, ROW_ITER>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_FWD_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_FWD_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_INV_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_INV_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// rows per row-kernel workgroup for length-N rows (FP32): the largest power
+// of two with at most 4096 points per workgroup, clamped to [8, 64]
+constexpr int row_s_big(int n) {
+  int s = 8;
+  while (s < 64 && 2 * s * n <= 4096) s *= 2;
+  return s;
+}
+
+}  // namespace pdk
+
+// Defines launch_col_<N> / launch_row_<N>.
+#define PD_INSTANTIATE(N)                                                                         \
+  namespace pdk {                                                                                 \
+  hipError_t launch_col_##N(int mode, int cols, int grid, int groups, const Vol* vols,            \
+                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st) { \
+    if (precision == 1) {                                                                         \
+      if (cols != 8) return hipErrorInvalidValue;                                                 \
+      return launch_col_t<N, double, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);            \
+    }                                                                                             \
+    if (cols == 16) return launch_col_t<N, float, 16>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (cols == 8) return launch_col_t<N, float, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);   \
+    return hipErrorInvalidValue;                                                                  \
+  }                                                                                               \
+  hipError_t launch_row_##N(int mode, int rows, int grid, int groups, const Vol* vols,            \
+                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st) { \
+    if (precision == 1) {                                                                         \
+      if (rows != 8) return hipErrorInvalidValue;                                                 \
+      return launch_row_t<N, double, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);            \
+    }                                                                                             \
+    constexpr int SB = row_s_big(N);                                                              \
+    if (rows == SB) return launch_row_t<N, float, SB>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if constexpr (SB != 8) {                                                                      \
+      if (rows == 8) return launch_row_t<N, float, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    }                                                                                             \
+    return hipErrorInvalidValue;                                                                  \
+  }                                                                                               \
+  }

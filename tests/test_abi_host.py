@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the header declares, and validates requests."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2006_09808_amd as pd
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "pd.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:pd_status|const char\*|double)\s+(pd_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string"):
+        assert name in fns
+    assert set(fns) == set(pd.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pd.load_library()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    assert pd.status_string(pd.PD_OK) == "ok"
+    for s in range(-9, 2):
+        assert isinstance(pd.status_string(s), str) and pd.status_string(s)
+
+
+@pytest.mark.parametrize("n", pd.SUPPORTED_SIZES)
+def test_supported_sizes_validate(n):
+    assert pd.validate(n, 8, 1) > 0
+    assert pd.validate(8, n, 3) > 0
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 12, 36, 100, 130, 258, 768, 1024])
+def test_unsupported_sizes_rejected(n):
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(n, 64, 1)
+    assert e.value.status == pd.PD_ERR_SIZE
+
+
+def test_step_condition_matches_oracle_reading():
+    # tau*sigma*max|D|^2 < 1 strictly; max|D| = 2/3 with B0 in-plane
+    pd.validate(64, 64, 1, tau=1.4, sigma=1.4)
+    for t in (1.5, 1.6):
+        with pytest.raises(pd.PdError) as e:
+            pd.validate(64, 64, 1, tau=t, sigma=t)
+        assert e.value.status == pd.PD_ERR_STEP
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, theta=-0.1)
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, tau=0.0)
+    # identity kernel: max|D| = 1
+    pd.validate(64, 64, 1, tau=0.9, sigma=0.9, kernel="identity")
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, tau=1.0, sigma=1.0, kernel="identity")
+
+
+@pytest.mark.parametrize("nx,ny,b0,vox", [(64, 64, (0, 1, 0), (1, 1)), (96, 48, (0.3, 0.5, 0.8), (0.72, 1.0)),
+                                          (8, 8, (1, 1, 0), (1, 1)), (24, 384, (0, 0, 1), (1, 2))])
+def test_kernel_norm_matches_oracle(nx, ny, b0, vox):
+    D = oracle.dipole_kernel(nx, ny, b0, vox)
+    assert pd.kernel_norm(nx, ny, b0, vox) == pytest.approx(oracle.kernel_norm(D), abs=1e-15)
+
+
+def test_argument_errors():
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, lam=-1.0)
+    assert e.value.status == pd.PD_ERR_ARG
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, lam=float("nan"))
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, gap_tol=1e-5, check_every=0)
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, max_iter=-1)
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, voxel=(0.0, 1.0))
+    with pytest.raises(pd.PdError):
+        pd.validate(64, 64, 1, delta_ptr=0)
+
+
+def test_state_bytes_model():
+    # four [P][ny][nx] complex FP32 fields (chi, dual, F delta, exchange): 16 B/voxel
+    b = pd.validate(256, 256, 64)
+    assert 64 * 256 * 256 * 16 <= b < 64 * 256 * 256 * 16 + (1 << 20)
+    b2 = pd.validate(256, 256, 64, gap_tol=1e-5)    # + a check exchange buffer
+    assert b2 - b >= 64 * 256 * 256 * 4
+    b64 = pd.validate(256, 256, 64, precision="fp64")
+    assert b64 >= 2 * 64 * 256 * 256 * 16
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = pd.load_library()
+    cfg = pd.pdlib.PdConfig()
+    cfg.arena = 1 << 20
+    cfg.arena_bytes = 1 << 20
+    ctx = ctypes.c_void_p()
+    assert lib.pd_create(ctypes.byref(cfg), ctypes.byref(ctx)) == pd.PD_ERR_NODEVICE
+    assert lib.pd_destroy(None) == pd.PD_OK

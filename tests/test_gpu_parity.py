@@ -1,0 +1,258 @@
+"""GPU parity: the HIP solver (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded phantoms; the field map is made by the oracle's own forward
+operator and rounded to FP32, and the same FP32 field map goes to both sides.
+Bar: relative L2 error on chi <= 1e-4 after a fixed iteration count
+(FP32 GPU arithmetic against FP64; the expected error is ~1e-6).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pd_inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def solver(torch_mod):
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0)
+    yield s
+    s.close()
+
+
+def make_case(seed, nz, ny, nx, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), **params):
+    w = pd_inputs.random_stack(seed, nz, ny, nx, **params)
+    w.b0, w.voxel = b0, voxel
+    field = oracle.forward(w.chi_true, b0=b0, voxel=voxel)
+    delta = pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)
+    return w, delta
+
+
+def gpu_solve(solver, torch, delta, **params):
+    d = torch.from_numpy(np.ascontiguousarray(delta)).to("cuda:0")
+    chi, info = solver.solve(d, **params)
+    return chi.cpu().numpy().astype(np.float64), info
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+APPLY_CASES = [
+    (3, 8, 8, (0, 1, 0), (1, 1)),
+    (2, 64, 64, (0, 1, 0), (1, 1)),
+    (3, 64, 96, (0.3, 0.5, 0.8), (0.72, 1.0)),
+    (2, 128, 192, (0, 1, 0), (1, 1)),
+    (1, 384, 24, (1, 1, 0), (1, 1)),
+    (2, 16, 512, (0, 1, 0), (1, 1)),
+    (2, 256, 256, (0, 1, 0), (1, 1)),
+    (5, 32, 48, (0, 0.6, 0.8), (1, 2)),
+    (1, 384, 384, (0, 1, 0), (1, 1)),
+]
+
+
+@pytest.mark.parametrize("nz,ny,nx,b0,vox", APPLY_CASES)
+def test_forward_operator_matches_oracle(solver, torch_mod, nz, ny, nx, b0, vox):
+    _say("apply_kernel nz=%d ny=%d nx=%d b0=%s voxel=%s" % (nz, ny, nx, b0, vox))
+    rng = np.random.default_rng(nz * 1000 + ny + nx)
+    x = rng.normal(size=(nz, ny, nx)).astype(np.float32)
+    ref = oracle.forward(x.astype(np.float64), b0=b0, voxel=vox)
+    xt = torch_mod.from_numpy(x).to("cuda:0")
+    out = solver.apply_kernel(xt, b0=b0, voxel=vox).cpu().numpy().astype(np.float64)
+    err = rel_l2(out, ref)
+    _say("  relL2 %.3e" % err)
+    assert err <= 1e-5
+
+
+SOLVE_CASES = [
+    # (seed, nz, ny, nx, params)
+    (1, 3, 64, 96, dict(lam=1e-3, max_iter=80, b0=(0.3, 0.5, 0.8), voxel=(0.72, 1.0))),
+    (2, 2, 192, 128, dict(lam=1e-3, max_iter=60)),
+    (3, 1, 24, 384, dict(lam=1e-3, max_iter=40)),
+    (4, 2, 16, 512, dict(lam=1e-3, max_iter=30)),
+    (5, 5, 48, 32, dict(lam=2e-3, max_iter=50, theta=0.5, tau=1.0, sigma=1.2)),
+    (6, 4, 128, 128, dict(lam=1e-3, max_iter=100)),
+    (7, 3, 256, 256, dict(lam=1e-3, max_iter=40)),
+]
+
+
+@pytest.mark.parametrize("seed,nz,ny,nx,params", SOLVE_CASES)
+def test_fixed_iterations_match_oracle(solver, torch_mod, seed, nz, ny, nx, params):
+    _say("solve seed=%d nz=%d ny=%d nx=%d %s" % (seed, nz, ny, nx, params))
+    p = dict(params)
+    b0 = p.pop("b0", (0.0, 1.0, 0.0))
+    vox = p.pop("voxel", (1.0, 1.0))
+    w, delta = make_case(seed, nz, ny, nx, b0=b0, voxel=vox, **p)
+    sp = w.solver_params()
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    ref, iref = oracle.solve(delta.astype(np.float64), **sp)
+    err = rel_l2(got, ref)
+    _say("  relL2 %.3e  max-abs %.3e ppm  P %.8e (oracle %.8e)" % (err, np.abs(got - ref).max(),
+                                                                  info["primal"], iref["primal"]))
+    assert info["iterations"] == iref["iterations"] == sp["max_iter"]
+    assert err <= REL_TOL
+    assert info["primal"] == pytest.approx(iref["primal"], rel=1e-4)
+
+
+def test_config1_plain_64x64(solver, torch_mod):
+    w = pd_inputs.config1()
+    field = oracle.forward(w.chi_true)
+    delta = pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)
+    sp = w.solver_params()
+    _say("config1 64x64x1, %d iterations" % sp["max_iter"])
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    ref, iref = oracle.solve(delta.astype(np.float64), **sp)
+    err = rel_l2(got, ref)
+    _say("  relL2 %.3e  max-abs %.3e ppm" % (err, np.abs(got - ref).max()))
+    assert err <= REL_TOL
+    assert info["iterations"] == 200
+
+
+def test_gap_report_matches_oracle(solver, torch_mod):
+    w, delta = make_case(11, 2, 64, 64, lam=1e-3, max_iter=40, gap_tol=1e-12, check_every=10)
+    sp = w.solver_params()
+    _say("gap report 64x64x2, 40 iterations, checks every 10")
+    hist = []
+    ref, iref = oracle.solve(delta.astype(np.float64), history=hist, **sp)
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    _say("  P %.10e / %.10e  D %.10e / %.10e  relgap %.6e / %.6e" % (
+        info["primal"], iref["primal"], info["dual"], iref["dual"], info["rel_gap"], iref["rel_gap"]))
+    assert info["iterations"] == 40
+    assert info["primal"] == pytest.approx(iref["primal"], rel=1e-5)
+    assert info["dual"] == pytest.approx(iref["dual"], rel=1e-4)
+    assert abs(info["rel_gap"] - iref["rel_gap"]) <= 1e-4 * max(1.0, abs(iref["rel_gap"]))
+    assert rel_l2(got, ref) <= REL_TOL
+
+
+def test_identity_kernel_tolerance_stop(solver, torch_mod):
+    rng = np.random.default_rng(21)
+    delta = rng.normal(size=(3, 32, 64)).astype(np.float32)
+    sp = dict(lam=0.2, tau=0.9, sigma=0.9, theta=1.0, max_iter=400, gap_tol=1e-5, check_every=5,
+              kernel="identity")
+    _say("identity kernel, gap_tol 1e-5")
+    hist = []
+    ref, iref = oracle.solve(delta.astype(np.float64), history=hist,
+                             **{k: v for k, v in sp.items() if k != "kernel"}, kind="identity")
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    _say("  oracle stop %d relgap %.3e; gpu stop %d relgap %.3e" % (
+        iref["iterations"], iref["rel_gap"], info["iterations"], info["rel_gap"]))
+    assert info["iterations"] < 400 and info["iterations"] % 5 == 0
+    assert info["rel_gap"] <= 1e-5
+    # the stop check can differ by one check period only when the oracle's gap
+    # lands within FP32 rounding of the tolerance
+    assert abs(info["iterations"] - iref["iterations"]) <= 5
+    ref_same, _ = oracle.solve(delta.astype(np.float64), kind="identity",
+                               **dict((k, v) for k, v in sp.items() if k not in ("kernel", "gap_tol")
+                                      and k != "max_iter"), max_iter=info["iterations"])
+    assert rel_l2(got, ref_same) <= REL_TOL
+    closed = np.sign(delta) * np.maximum(np.abs(delta.astype(np.float64)) - 0.2, 0.0)
+    assert np.max(np.abs(got - closed)) <= 1e-3
+
+
+def test_zero_iterations(solver, torch_mod):
+    w, delta = make_case(12, 3, 32, 32, max_iter=0)
+    sp = w.solver_params()
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    ref, iref = oracle.solve(delta.astype(np.float64), **sp)
+    assert info["iterations"] == 0
+    assert np.all(got == 0.0)
+    assert info["primal"] == pytest.approx(iref["primal"], rel=1e-5)
+    assert info["rel_gap"] == pytest.approx(1.0, abs=1e-6)
+
+
+def test_batch_results_equal_solo_results(solver, torch_mod):
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    cases = [make_case(31, 3, 64, 64, max_iter=37), make_case(32, 2, 96, 64, max_iter=55),
+             make_case(33, 1, 64, 64, max_iter=20, gap_tol=1e-9, check_every=10)]
+    _say("batch of 3 requests (two shapes) vs solo")
+    solo = []
+    for w, d in cases:
+        got, info = gpu_solve(solver, torch, d, **w.solver_params())
+        solo.append((got, info))
+    jobs = []
+    for w, d in cases:
+        dt = torch.from_numpy(d).to("cuda:0")
+        jobs.append((dt, torch.empty_like(dt), w.solver_params()))
+    tickets = solver.submit(jobs)
+    for (dt, chi, _), t, (sgot, sinfo) in zip(jobs, tickets, solo):
+        info = solver.poll(t, -1)
+        assert info["status"] == pd.PD_OK
+        assert info["iterations"] == sinfo["iterations"]
+        np.testing.assert_array_equal(chi.cpu().numpy().astype(np.float64), sgot)
+
+
+def test_deterministic_bitwise(solver, torch_mod):
+    w, delta = make_case(41, 4, 128, 64, max_iter=30)
+    a, _ = gpu_solve(solver, torch_mod, delta, **w.solver_params())
+    b, _ = gpu_solve(solver, torch_mod, delta, **w.solver_params())
+    np.testing.assert_array_equal(a, b)
+
+
+def test_nonfinite_input_reported(solver, torch_mod):
+    import paper_2006_09808_amd as pd
+    delta = np.zeros((2, 32, 32), dtype=np.float32)
+    delta[1, 5, 7] = np.nan
+    d = torch_mod.from_numpy(delta).to("cuda:0")
+    chi = torch_mod.empty_like(d)
+    (t,) = solver.submit([(d, chi, dict(max_iter=20, gap_tol=1e-6, check_every=5))])
+    info = solver.poll(t, -1)
+    assert info["status"] == pd.PD_ERR_NONFINITE
+
+
+def test_budget_and_queueing(torch_mod):
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    need = pd.validate(64, 64, 4)
+    # room for one request at a time: the others wait in the queue
+    with pd.Solver(arena_bytes=need + (need // 2) + (1 << 20), device=0) as s:
+        with pytest.raises(pd.PdError) as e:
+            big = torch.zeros((64, 256, 256), device="cuda:0")
+            s.submit([(big, torch.empty_like(big), dict(max_iter=1))])
+        assert e.value.status == pd.PD_ERR_BUDGET
+        cases = [make_case(50 + i, 4, 64, 64, max_iter=25) for i in range(3)]
+        jobs = []
+        for w, d in cases:
+            dt = torch.from_numpy(d).to("cuda:0")
+            jobs.append((dt, torch.empty_like(dt), w.solver_params()))
+        tickets = s.submit(jobs)
+        for (dt, chi, _), t, (w, d) in zip(jobs, tickets, cases):
+            info = s.poll(t, -1)
+            assert info["status"] == pd.PD_OK and info["iterations"] == 25
+            ref, _ = oracle.solve(d.astype(np.float64), **w.solver_params())
+            assert rel_l2(chi.cpu().numpy().astype(np.float64), ref) <= REL_TOL
+
+
+def test_batched_config_full_size_sampled(solver, torch_mod):
+    """64 slices of 256x256, 500 iterations, one batched solve; in fixed-count
+    mode slices are independent, so sampled slices are checked against the
+    oracle solved on those slices alone."""
+    w = pd_inputs.config2()
+    _say("batched 256x256x64, 500 iterations (sampled slices vs oracle)")
+    field = oracle.forward(w.chi_true)
+    delta = pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)
+    sp = w.solver_params()
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    assert info["iterations"] == 500
+    for z in (0, 37, 63):
+        ref, _ = oracle.solve(delta[z:z + 1].astype(np.float64), **sp)
+        err = rel_l2(got[z:z + 1], ref)
+        _say("  slice %d relL2 %.3e max-abs %.3e" % (z, err, np.abs(got[z] - ref[0]).max()))
+        assert err <= REL_TOL
