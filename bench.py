@@ -41,7 +41,51 @@ def parse():
     ap.add_argument("--no-per-slice", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=16)
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only time a plain device copy of BYTES bytes (the reference kernel for "
+                         "scaling hardware byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(nbytes, reps=5):
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_bytes": nbytes, "read_plus_write_GBs": 2 * nbytes / dt / 1e9,
+                      "ms": dt * 1e3}), flush=True)
+
+
+KERNEL_SOURCES = ("paper_2006_09808_amd/csrc/pd_fft.hpp", "paper_2006_09808_amd/csrc/pd_kern_impl.hpp",
+                  "paper_2006_09808_amd/csrc/pd_internal.hpp")
+PROFILE = "profiles/pd_iteration_kernels_256x256x64.md"
+
+
+def measured_traffic(kernel):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from the
+    committed rocprofv3 summary, or None if the kernel sources changed since
+    the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in KERNEL_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        with open(os.path.join(ROOT, PROFILE)) as fh:
+            lines = [l.strip() for l in fh if l.strip().startswith("traffic:")]
+    except OSError:
+        return None
+    for l in lines:
+        rec = json.loads(l[len("traffic:"):])
+        if rec.get("kernel") == kernel and rec.get("sources_sha256_16") == h.hexdigest()[:16]:
+            return rec["read_bytes"] + rec["write_bytes"]
+    return None
 
 
 def cpu_baseline(w, nslices, iters):
@@ -69,6 +113,9 @@ def cpu_baseline(w, nslices, iters):
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path to measure "
               "(requests would be sharded across GPUs with no exchange inside a solve)", file=sys.stderr)
@@ -153,7 +200,8 @@ def main():
             "speedup_batched": (vit / per_slice) and value / (vit / per_slice)},
         "roofline": {"bound": "hbm", "kernel": "column" if dom_is_col else "row",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("column" if dom_is_col else "row"),
                      "avg_ms": col_avg if dom_is_col else row_avg,
                      "column_kernel": {"launches": ncol, "avg_ms": col_avg, "GBs": col_gbs},
                      "row_kernel": {"launches": nrow, "avg_ms": row_avg, "GBs": row_gbs}},
