@@ -56,8 +56,14 @@ enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1 };  /* pd_request.kernel   *
 
 /* pd_config.flags */
 enum {
-  PD_FLAG_TIME_KERNELS = 1   /* time every launch of the iteration kernels with
+  PD_FLAG_TIME_KERNELS = 1,  /* time every launch of the iteration kernels with
                                 HIP events on the context stream (pd_kernel_time) */
+  PD_FLAG_NO_RESIDENT = 2,   /* never use the resident multi-iteration kernel:
+                                two launches per iteration for every shape     */
+  PD_FLAG_FENCED_EXCHANGE = 4 /* resident kernel: always exchange between the
+                                workgroups of a team with agent-scope
+                                release/acquire (L2 write-back), even when
+                                they share an XCD                              */
 };
 
 typedef struct pd_ctx pd_ctx;     /* opaque, library-owned */
@@ -71,8 +77,9 @@ typedef struct {
   size_t arena_bytes;
   int max_slots;       /* most requests resident on the GPU at once; 0 = no cap  */
   int precision;       /* PD_FP32 (default) or PD_FP64                            */
-  int step_iters;      /* iterations launched between host scheduling points;
-                          0 = default (10)                                         */
+  int step_iters;      /* most iterations launched between host scheduling points
+                          (requests are admitted and retired only there); a step
+                          also ends at every request's next gap check; 0 = 100   */
   int flags;           /* PD_FLAG_* */
 } pd_config;
 
@@ -149,12 +156,13 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r);
 /* Seconds on a monotonic clock (the clock of pd_result's time stamps). */
 double pd_now(void);
 
-/* With PD_FLAG_TIME_KERNELS: number of launches and summed HIP-event time in
- * milliseconds of one kernel class since the last reset.  kind: 0 = column
- * kernel (forward column FFT, dual prox, inverse column FFT), 1 = row kernel
- * (inverse row FFT, primal prox, over-relaxation, forward row FFT).
- * pd_kernel_time_reset clears both. */
-pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms);
+/* With PD_FLAG_TIME_KERNELS: number of launches, summed HIP-event time in
+ * milliseconds, and summed iterations x slice-pair points of one kernel class
+ * since the last reset.  kind: 0 = column kernel (forward column FFT, dual
+ * prox, inverse column FFT), 1 = row kernel (inverse row FFT, primal prox,
+ * over-relaxation, forward row FFT), 2 = resident kernel (a whole step of
+ * iterations of square slices kept on chip).  pd_kernel_time_reset clears all. */
+pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 
 /* Bytes of arena currently in use and the number of resident requests. */

@@ -10,5 +10,5 @@ from .pdlib import (  # noqa: F401
     make_request, LIB_PATH, EXPORTS, SUPPORTED_SIZES,
     PD_OK, PD_PENDING, PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET,
     PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE,
-    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW,
+    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, PD_FLAG_NO_RESIDENT,
 )

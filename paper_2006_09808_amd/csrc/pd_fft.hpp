@@ -271,6 +271,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------------------
 template <typename T, int N, int S, int NT, bool COLS>
 struct Fft {
+  static constexpr int kNT = NT;
   static constexpr int LDN = N + N / 32 + 1;                 // padded row (rows layout)
   static constexpr int LDS_ELEMS = COLS ? N * (S + 1) : S * LDN;
 

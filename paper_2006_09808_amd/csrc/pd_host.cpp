@@ -36,7 +36,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSlots = 256;
-constexpr int kMaxStep = 64;   // check_mask has 64 bits
+constexpr int kDefaultStep = 100;
+constexpr int kMaxStep = 1 << 20;
+constexpr int kMaxCounters = 4096;   // team barrier counters per resident launch (2 per team)
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline bool isfin(double x) { return std::isfinite(x); }
@@ -138,8 +140,11 @@ Layout layout_of(const pd_request& r, int precision) {
   L.off_dhat = o; o += L.field;
   L.off_ex = o; o += L.field;
   if (L.separate_ex2) { L.off_ex2 = o; o += L.field; } else { L.off_ex2 = L.off_ex; }
-  L.off_prow = o; o += align_up((size_t)L.P * L.row_groups * 2 * sizeof(double));
-  L.off_pcol = o; o += align_up((size_t)L.P * L.col_groups * 3 * sizeof(double));
+  // gap partials: one entry per workgroup of either the two-launch kernels
+  // or the resident team (at most 16 workgroups per pair)
+  size_t pg = (size_t)std::max(std::max(L.row_groups, L.col_groups), 16);
+  L.off_prow = o; o += align_up((size_t)L.P * pg * 2 * sizeof(double));
+  L.off_pcol = o; o += align_up((size_t)L.P * pg * 3 * sizeof(double));
   L.total = o;
   return L;
 }
@@ -297,7 +302,11 @@ struct pd_ctx {
   Vol* d_vols = nullptr;       // nslots + 1
   Ctl* d_ctl = nullptr;        // nslots + 1
   int* d_slots = nullptr;      // nslots
-  Range* d_ranges = nullptr;   // nslots + 1
+  Range* d_ranges = nullptr;   // range_cap
+  size_t range_cap = 0;        // entries of d_ranges / h_ranges; the last is pd_apply_kernel's
+  unsigned* d_counters = nullptr;   // kMaxCounters team-barrier counters
+  int* d_abort = nullptr;           // set by a resident launch whose barrier timed out
+  int* h_abort = nullptr;
   Vol* h_vols = nullptr;
   Ctl* h_ctl = nullptr;
   int* h_slots = nullptr;
@@ -306,8 +315,9 @@ struct pd_ctx {
   // kernel timing
   bool time_kernels = false;
   std::mutex tmu;
-  int64_t t_launches[2] = {0, 0};
-  double t_ms[2] = {0.0, 0.0};
+  int64_t t_launches[3] = {0, 0, 0};
+  double t_ms[3] = {0.0, 0.0, 0.0};
+  double t_points[3] = {0.0, 0.0, 0.0};   // iterations x slice-pair points processed
   std::vector<hipEvent_t> ev_pool;
 };
 
@@ -482,7 +492,7 @@ hipError_t setup_job(pd_ctx* c, Job& j) {
 // entries are already on the device.
 hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
   hipError_t e;
-  for (size_t k = 0; k < js.size(); ++k) c->h_ranges[k] = Range{js[k]->slot, 0};
+  for (size_t k = 0; k < js.size(); ++k) c->h_ranges[k] = Range{js[k]->slot, 0, 0, 0};
   if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, js.size() * sizeof(Range), hipMemcpyHostToDevice,
                           c->stream)) != hipSuccess)
     return e;
@@ -505,71 +515,134 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
   return hipStreamSynchronize(c->stream);
 }
 
-// One scheduling step over all resident jobs.  Returns HIP status.
+// One scheduling step over all resident jobs: K iterations for every job,
+// where K ends the step at every job's next gap check (or its last
+// iteration), so checks and stop decisions only happen at step ends.
 hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
-  bool any_gap = false;
-  for (auto& j : act) any_gap |= j->req.gap_tol > 0;
-  int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : (any_gap ? 10 : 50);
-  K = std::min(K, kMaxStep);
+  int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : kDefaultStep;
+  bool any_check_only = false;
+  for (auto& j : act) {
+    if (j->req.max_iter == 0) {
+      any_check_only = true;
+      continue;
+    }
+    int rem = j->req.max_iter - j->done_iters;
+    int nc = j->req.gap_tol > 0 ? j->req.check_every - j->done_iters % j->req.check_every : rem;
+    K = std::min(K, std::min(rem, nc));
+  }
+  if (any_check_only) K = 1;
+  K = std::max(K, 1);
 
-  // group resident jobs by slice shape; build descriptors and range tables
+  // descriptors
   std::map<GroupKey, std::vector<Job*>> groups;
-  for (auto& j : act) groups[GroupKey{j->req.nx, j->req.ny}].push_back(j.get());
-  hipError_t e;
-  struct Launch {
-    int nx, ny, rows, cols, rg, cg;
-    int range_off, nranges, npairs;
-  };
-  std::vector<Launch> launches;
-  int k = 0;
   int nslot_list = 0;
-  uint64_t any_check = 0;
-  for (auto& g : groups) {
-    Launch L{};
-    L.nx = g.first.nx;
-    L.ny = g.first.ny;
-    L.range_off = k;
-    for (Job* j : g.second) {
-      L.rows = j->L.rows;
-      L.cols = j->L.cols;
-      L.rg = j->L.row_groups;
-      L.cg = j->L.col_groups;
-      c->h_ranges[k++] = Range{j->slot, L.npairs};   // first pair; scaled per kernel below
-      L.npairs += j->L.P;
-      Vol& V = c->h_vols[j->slot];
-      fill_vol(c, *j, V);
+  bool any_check = false;
+  for (auto& j : act) {
+    groups[GroupKey{j->req.nx, j->req.ny}].push_back(j.get());
+    Vol& V = c->h_vols[j->slot];
+    fill_vol(c, *j, V);
+    if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
+      V.iters = 1;
+      V.done_base = -1;
+      V.final_it = 0;
+      V.check_last = 1;
+      V.check_only = 1;
+    } else {
       int rem = j->req.max_iter - j->done_iters;
       V.iters = std::min(K, rem);
       V.done_base = j->done_iters;
-      V.final_it = (rem <= K) ? rem - 1 : -1;
-      V.check_mask = 0;
-      for (int it = 0; it < V.iters; ++it) {
-        int n = j->done_iters + it + 1;
-        if ((j->req.gap_tol > 0 && n % j->req.check_every == 0) || n == j->req.max_iter)
-          V.check_mask |= (1ull << it);
-      }
-      if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
-        V.iters = 1;
-        V.done_base = -1;
-        V.final_it = 0;
-        V.check_mask = 1;
-        V.check_only = 1;
-      }
-      any_check |= V.check_mask;
-      c->h_slots[nslot_list++] = j->slot;
+      V.final_it = (rem == V.iters) ? V.iters - 1 : -1;
+      int n = j->done_iters + V.iters;
+      V.check_last = (j->req.gap_tol > 0 && n % j->req.check_every == 0) || n == j->req.max_iter;
     }
-    L.nranges = k - L.range_off;
-    launches.push_back(L);
+    any_check |= V.check_last != 0;
+    c->h_slots[nslot_list++] = j->slot;
   }
-  // Range.first counts pairs; the column and row kernels need it in
-  // workgroups, so keep one table per kernel kind: [0, k) rows, [k, 2k) cols.
-  for (int i = 0; i < k; ++i) c->h_ranges[k + i] = c->h_ranges[i];
-  for (auto& L : launches)
-    for (int i = 0; i < L.nranges; ++i) {
-      c->h_ranges[L.range_off + i].first *= L.rg;
-      c->h_ranges[k + L.range_off + i].first *= L.cg;
+
+  // launch plan: per shape either one resident launch per batch of pairs that
+  // can be co-resident, or K x (column, row) launches covering every pair
+  struct Launch {
+    int nx, ny, rows, cols, rg, cg;
+    bool resident;
+    int team;
+    int range_off, nranges, npairs;          // resident: one range table
+    int row_off, col_off;                    // two-launch path: row and column tables
+  };
+  std::vector<Launch> launches;
+  size_t k = 0;
+  auto push_range = [&](int slot, int first, int pair0) -> bool {
+    if (k + 1 >= c->range_cap) return false;
+    c->h_ranges[k++] = Range{slot, first, pair0, 0};
+    return true;
+  };
+  bool fits = true;
+  for (auto& g : groups) {
+    int nx = g.first.nx, ny = g.first.ny;
+    int team = (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only)
+                   ? resident_team(nx) : 0;
+    int maxt = team ? std::min(resident_max_teams(nx), kMaxCounters / 2) : 0;
+    if (team && maxt > 0) {
+      // split the shape's pairs into co-resident batches
+      Launch L{};
+      L.nx = nx;
+      L.ny = ny;
+      L.resident = true;
+      L.team = team;
+      L.range_off = (int)k;
+      for (Job* j : g.second) {
+        int p = 0;
+        while (p < j->L.P) {
+          if (L.npairs == maxt) {
+            L.nranges = (int)k - L.range_off;
+            launches.push_back(L);
+            L.range_off = (int)k;
+            L.npairs = 0;
+          }
+          int take = std::min(j->L.P - p, maxt - L.npairs);
+          fits &= push_range(j->slot, L.npairs * team, p);
+          L.npairs += take;
+          p += take;
+        }
+      }
+      L.nranges = (int)k - L.range_off;
+      if (L.npairs > 0) launches.push_back(L);
+    } else {
+      Launch L{};
+      L.nx = nx;
+      L.ny = ny;
+      L.resident = false;
+      L.row_off = (int)k;
+      int np = 0;
+      for (Job* j : g.second) {
+        L.rows = j->L.rows;
+        L.cols = j->L.cols;
+        L.rg = j->L.row_groups;
+        L.cg = j->L.col_groups;
+        fits &= push_range(j->slot, np * L.rg, 0);
+        np += j->L.P;
+      }
+      L.npairs = np;
+      L.nranges = (int)g.second.size();
+      L.col_off = (int)k;
+      np = 0;
+      for (Job* j : g.second) {
+        fits &= push_range(j->slot, np * L.cg, 0);
+        np += j->L.P;
+      }
+      launches.push_back(L);
     }
-  if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, sizeof(Range) * 2 * k, hipMemcpyHostToDevice, c->stream)) !=
+  }
+  if (!fits) return hipErrorOutOfMemory;   // range table too small: cannot happen with range_cap
+  // resident launches report gap partials per team member
+  for (auto& L : launches)
+    if (L.resident)
+      for (int i = 0; i < L.nranges; ++i) {
+        Vol& V = c->h_vols[c->h_ranges[L.range_off + i].slot];
+        V.row_groups = V.col_groups = L.team;
+      }
+
+  hipError_t e;
+  if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, sizeof(Range) * k, hipMemcpyHostToDevice, c->stream)) !=
       hipSuccess)
     return e;
   if ((e = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * c->nslots, hipMemcpyHostToDevice, c->stream)) !=
@@ -579,60 +652,97 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
                           c->stream)) != hipSuccess)
     return e;
 
-  int kmax = 0;
-  for (auto& j : act) kmax = std::max(kmax, c->h_vols[j->slot].iters);
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
-  for (int it = 0; it < kmax; ++it) {
-    for (auto& L : launches) {
-      const Range* rrow = c->d_ranges + L.range_off;
-      const Range* rcol = c->d_ranges + k + L.range_off;
-      for (int kind = 0; kind < 2; ++kind) {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (c->time_kernels) {
-          e0 = get_event(c);
-          e1 = get_event(c);
-          if (e0) (void)hipEventRecord(e0, c->stream);
-        }
-        if (kind == 0)
-          e = launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
-                         c->precision, c->stream);
-        else
-          e = launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl, it,
-                         c->precision, c->stream);
+  std::vector<double> ev_points;
+  auto timed = [&](int kind, double points, auto&& fn) -> hipError_t {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->time_kernels) {
+      e0 = get_event(c);
+      e1 = get_event(c);
+      if (e0) (void)hipEventRecord(e0, c->stream);
+    }
+    hipError_t r = fn();
+    if (c->time_kernels && e0 && e1) {
+      (void)hipEventRecord(e1, c->stream);
+      evs.push_back({kind, {e0, e1}});
+      ev_points.push_back(points);
+    }
+    return r;
+  };
+
+  // resident launches first (each runs all K iterations of its pairs)
+  for (auto& L : launches) {
+    if (!L.resident) continue;
+    if ((e = launch_zero(c->d_counters, align_up(2 * sizeof(unsigned) * (size_t)L.npairs), c->stream)) !=
+        hipSuccess)
+      return e;
+    const Range* rr = c->d_ranges + L.range_off;
+    double pts = (double)L.npairs * L.nx * L.ny * K;
+    const int fenced = (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0;
+    e = timed(2, pts, [&] {
+      return launch_resident(L.nx, L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort,
+                             fenced, c->stream);
+    });
+    if (e != hipSuccess) return e;
+  }
+  // two-launch path
+  bool any_two = false;
+  for (auto& L : launches) any_two |= !L.resident;
+  if (any_two) {
+    for (int it = 0; it < K; ++it) {
+      for (auto& L : launches) {
+        if (L.resident) continue;
+        const Range* rrow = c->d_ranges + L.row_off;
+        const Range* rcol = c->d_ranges + L.col_off;
+        double pts = (double)L.npairs * L.nx * L.ny;
+        e = timed(0, pts, [&] {
+          return launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
+                            c->precision, c->stream);
+        });
         if (e != hipSuccess) return e;
-        if (c->time_kernels && e0 && e1) {
-          (void)hipEventRecord(e1, c->stream);
-          evs.push_back({kind, {e0, e1}});
-        }
+        e = timed(1, pts, [&] {
+          return launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl, it,
+                            c->precision, c->stream);
+        });
+        if (e != hipSuccess) return e;
       }
     }
-    if ((any_check >> it) & 1ull) {
+    if (any_check) {
       for (auto& L : launches) {
-        const Range* rcol = c->d_ranges + k + L.range_off;
-        e = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
+        if (L.resident) continue;
+        const Range* rcol = c->d_ranges + L.col_off;
+        e = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, K - 1,
                        c->precision, c->stream);
         if (e != hipSuccess) return e;
       }
-      e = launch_reduce(nslot_list, c->d_vols, c->d_slots, c->d_ctl, it, c->precision, c->stream);
-      if (e != hipSuccess) return e;
     }
+  }
+  if (any_check) {
+    // check-only volumes have iters == 1: their reduction runs at it == 0 == K - 1
+    e = launch_reduce(nslot_list, c->d_vols, c->d_slots, c->d_ctl, K - 1, c->precision, c->stream);
+    if (e != hipSuccess) return e;
   }
   if ((e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl) * c->nslots, hipMemcpyDeviceToHost, c->stream)) !=
       hipSuccess)
     return e;
+  if ((e = hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+    return e;
   if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
   if (!evs.empty()) {
     std::lock_guard<std::mutex> lk(c->tmu);
-    for (auto& x : evs) {
+    for (size_t i = 0; i < evs.size(); ++i) {
+      auto& x = evs[i];
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
         c->t_launches[x.first]++;
         c->t_ms[x.first] += ms;
+        c->t_points[x.first] += ev_points[i];
       }
       c->ev_pool.push_back(x.second.first);
       c->ev_pool.push_back(x.second.second);
     }
   }
+  if (*c->h_abort) return hipErrorLaunchTimeOut;   // a team barrier gave up
   return hipSuccess;
 }
 
@@ -809,8 +919,10 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->time_kernels = (cfg->flags & PD_FLAG_TIME_KERNELS) != 0;
   c->arena.init((char*)cfg->arena, cfg->arena_bytes);
 
+  c->range_cap = 4 * (size_t)c->nslots + 4096;
   c->ctl_bytes = align_up(sizeof(Vol) * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
-                 align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * (2 * c->nslots + 1));
+                 align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * c->range_cap) +
+                 align_up(sizeof(unsigned) * kMaxCounters) + align_up(sizeof(int));
   if (!c->arena.alloc(c->ctl_bytes, &c->ctl_off)) return PD_ERR_BUDGET;
   char* p = c->arena.ptr(c->ctl_off);
   c->d_vols = (Vol*)p;
@@ -820,6 +932,10 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->d_slots = (int*)p;
   p += align_up(sizeof(int) * c->nslots);
   c->d_ranges = (Range*)p;
+  p += align_up(sizeof(Range) * c->range_cap);
+  c->d_counters = (unsigned*)p;
+  p += align_up(sizeof(unsigned) * kMaxCounters);
+  c->d_abort = (int*)p;
 
   if (cfg->stream) {
     c->stream = (hipStream_t)cfg->stream;
@@ -830,15 +946,17 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   if (hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_slots, sizeof(int) * c->nslots, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * (2 * c->nslots + 1), hipHostMallocDefault) !=
-          hipSuccess) {
+      hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * c->range_cap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_abort, sizeof(int), hipHostMallocDefault) != hipSuccess) {
     if (c->h_vols) (void)hipHostFree(c->h_vols);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->h_slots) (void)hipHostFree(c->h_slots);
     if (c->h_ranges) (void)hipHostFree(c->h_ranges);
+    if (c->h_abort) (void)hipHostFree(c->h_abort);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return PD_ERR_HIP;
   }
+  *c->h_abort = 0;
   std::memset(c->h_vols, 0, sizeof(Vol) * (c->nslots + 1));
   std::memset(c->h_ctl, 0, sizeof(Ctl) * (c->nslots + 1));
   for (int s = c->nslots - 1; s >= 0; --s) c->free_slots.push_back(s);
@@ -846,11 +964,13 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   if (hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * (c->nslots + 1), hipMemcpyHostToDevice, c->stream) !=
           hipSuccess ||
       launch_zero(c->d_ctl, sizeof(Ctl) * (c->nslots + 1), c->stream) != hipSuccess ||
+      launch_zero(c->d_abort, align_up(sizeof(int)), c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess) {
     (void)hipHostFree(c->h_vols);
     (void)hipHostFree(c->h_ctl);
     (void)hipHostFree(c->h_slots);
     (void)hipHostFree(c->h_ranges);
+    (void)hipHostFree(c->h_abort);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return PD_ERR_HIP;
   }
@@ -928,6 +1048,7 @@ pd_status pd_destroy(pd_ctx* c) {
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   if (c->h_slots) (void)hipHostFree(c->h_slots);
   if (c->h_ranges) (void)hipHostFree(c->h_ranges);
+  if (c->h_abort) (void)hipHostFree(c->h_abort);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return PD_OK;
@@ -976,9 +1097,9 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
       e = c->precision == PD_FP64 ? upload_table<double>(c, j.key, j.tab) : upload_table<float>(c, j.key, j.tab);
     Vol& V = c->h_vols[j.slot];
     fill_vol(c, j, V);
-    Range* hr = c->h_ranges + 2 * c->nslots;
-    *hr = Range{j.slot, 0};
-    const Range* dr = c->d_ranges + 2 * c->nslots;
+    Range* hr = c->h_ranges + (c->range_cap - 1);
+    *hr = Range{j.slot, 0, 0, 0};
+    const Range* dr = c->d_ranges + (c->range_cap - 1);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
@@ -1005,19 +1126,23 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
   return PD_OK;
 }
 
-pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms) {
-  if (!c || kind < 0 || kind > 1) return PD_ERR_ARG;
+pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters) {
+  if (!c || kind < 0 || kind > 2) return PD_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->tmu);
   if (launches) *launches = c->t_launches[kind];
   if (total_ms) *total_ms = c->t_ms[kind];
+  if (point_iters) *point_iters = c->t_points[kind];
   return PD_OK;
 }
 
 pd_status pd_kernel_time_reset(pd_ctx* c) {
   if (!c) return PD_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->tmu);
-  c->t_launches[0] = c->t_launches[1] = 0;
-  c->t_ms[0] = c->t_ms[1] = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    c->t_launches[k] = 0;
+    c->t_ms[k] = 0.0;
+    c->t_points[k] = 0.0;
+  }
   return PD_OK;
 }
 

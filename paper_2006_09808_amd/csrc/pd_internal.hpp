@@ -36,7 +36,8 @@ struct Vol {
   int row_groups;     // row-kernel workgroups per pair
   int col_groups;     // column-kernel workgroups per pair
   int check_only;     // max_iter == 0: only the gap of chi_0 = 0 is evaluated
-  uint64_t check_mask;  // bit `it`: gap partials after step iteration `it`
+  int check_last;     // gap partials after the step's last iteration
+  int pad0;
 };
 
 // Device-side control/result block of one resident request.
@@ -49,16 +50,18 @@ struct Ctl {
 };
 
 // One volume's share of a launch: workgroups [first, next range's first)
-// belong to volume `slot`, `groups` consecutive workgroups per pair.
+// belong to volume `slot`, `groups` consecutive workgroups per pair,
+// starting at pair `pair0`.
 struct Range {
   int slot;
   int first;
+  int pair0;          // first pair of the volume covered by this range
+  int pad;
 };
 
-// Workgroup -> (slot, pair, group) by binary search over the launch's ranges.
-__device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int nranges, int groups,
-                                          int& slot, int& pair, int& g) {
-  const int b = (int)blockIdx.x;
+// Workgroup b -> (slot, pair, group) by binary search over the launch's ranges.
+__device__ __forceinline__ void find_work_b(const Range* __restrict__ ranges, int nranges, int groups, int b,
+                                            int& slot, int& pair, int& g) {
   int lo = 0, hi = nranges - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
@@ -67,8 +70,13 @@ __device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int 
   }
   slot = ranges[lo].slot;
   int local = b - ranges[lo].first;
-  pair = local / groups;
-  g = local - pair * groups;
+  int p = local / groups;
+  g = local - p * groups;
+  pair = ranges[lo].pair0 + p;
+}
+__device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int nranges, int groups,
+                                          int& slot, int& pair, int& g) {
+  find_work_b(ranges, nranges, groups, (int)blockIdx.x, slot, pair, g);
 }
 
 enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3 };
@@ -93,5 +101,16 @@ hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl
 hipError_t launch_store_chi(const Vol* vols, int slot, size_t npairs_pts, int precision,
                             hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+// Resident (multi-iteration, cooperative) launch for square n x n slices.
+// resident_team(n) is the workgroups per pair (0: no resident kernel for n);
+// resident_max_teams(n) the teams that can be co-resident on the device.
+// Teams are placed one XCD apart (team t on XCD t mod 8), so a launch covers
+// a multiple of 8 teams; resident_max_teams is such a multiple.
+constexpr int kXcds = 8;
+int resident_team(int n);
+int resident_max_teams(int n);
+hipError_t launch_resident(int n, int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                           unsigned* counters, int* abort_flag, int fenced, hipStream_t st);
 
 }  // namespace pdk

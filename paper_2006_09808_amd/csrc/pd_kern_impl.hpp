@@ -30,12 +30,13 @@ __device__ __forceinline__ T clampv(T v, T lo, T hi) {
   return v < lo ? lo : (v > hi ? hi : v);
 }
 
-// Block-wide reduction of NV doubles (sum, or max for entries with MAXMASK
-// bit set); fixed tree, so the result is deterministic.  Result valid in
-// thread 0.  Uses its own LDS.
-template <int NV, int MAXMASK>
+// Block-wide reduction of NV doubles over NT threads (sum, or max for entries
+// with MAXMASK bit set); fixed tree, so the result is deterministic.  Result
+// valid in thread 0.  Uses its own LDS.
+template <int NV, int MAXMASK, int NT = kThreads>
 __device__ __forceinline__ void block_reduce(double (&v)[NV], int tid) {
-  __shared__ double red[NV][kThreads / 64];
+  static_assert(NT % 64 == 0, "whole waves");
+  __shared__ double red[NV][NT / 64];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double x = v[i];
@@ -52,7 +53,7 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], int tid) {
     for (int i = 0; i < NV; ++i) {
       double x = red[i][0];
 #pragma unroll
-      for (int w = 1; w < kThreads / 64; ++w) x = ((MAXMASK >> i) & 1) ? fmax(x, red[i][w]) : x + red[i][w];
+      for (int w = 1; w < NT / 64; ++w) x = ((MAXMASK >> i) & 1) ? fmax(x, red[i][w]) : x + red[i][w];
       v[i] = x;
     }
   }
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
   if constexpr (MODE == COL_ITER) {
     if (ctl[slot].stop || it >= V.iters || V.check_only) return;
   } else if constexpr (MODE == COL_CHECK) {
-    if (ctl[slot].stop || it >= V.iters || !((V.check_mask >> it) & 1ull)) return;
+    if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
   }
   const int nx = V.nx;
   const int c0 = g * S;
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       const T tau = (T)V.tau;
       const T tl = (T)(V.tau * V.lam);
       const T theta = (T)V.theta;
-      const bool check = (V.check_mask >> it) & 1ull;
+      const bool check = V.check_last && it == V.iters - 1;
       const bool last = (it == V.final_it);
       cpx<T>* __restrict__ chi = (cpx<T>*)V.chi + base;
       cpx<T> c[F::template nq<QO>()][QO];

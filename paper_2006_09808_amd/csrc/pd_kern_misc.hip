@@ -22,6 +22,43 @@ PD_DECL(384)
 PD_DECL(512)
 #undef PD_DECL
 
+#define PD_DECL_RES(N)                                                                                     \
+  hipError_t launch_resident_##N(int, const Vol*, const Range*, int, Ctl*, unsigned*, int*, int, hipStream_t); \
+  int resident_team_##N();                                                                                  \
+  int resident_max_teams_##N();
+PD_DECL_RES(64)
+PD_DECL_RES(128)
+PD_DECL_RES(256)
+#undef PD_DECL_RES
+
+int resident_team(int n) {
+  switch (n) {
+    case 64: return resident_team_64();
+    case 128: return resident_team_128();
+    case 256: return resident_team_256();
+    default: return 0;
+  }
+}
+
+int resident_max_teams(int n) {
+  switch (n) {
+    case 64: return resident_max_teams_64();
+    case 128: return resident_max_teams_128();
+    case 256: return resident_max_teams_256();
+    default: return 0;
+  }
+}
+
+hipError_t launch_resident(int n, int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                           unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {
+  switch (n) {
+    case 64: return launch_resident_64(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
+    case 128: return launch_resident_128(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
+    case 256: return launch_resident_256(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 bool size_supported(int n) {
   switch (n) {
     case 8: case 16: case 24: case 32: case 48: case 64: case 96:
@@ -68,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Vol* __restrict__ vol
   const int tid = threadIdx.x;
   const int slot = slots[blockIdx.x];
   const Vol& V = vols[slot];
-  if (ctl[slot].stop || it >= V.iters || !((V.check_mask >> it) & 1ull)) return;
+  if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
   const int nr = V.P * V.row_groups, nc = V.P * V.col_groups;
   double l1 = 0.0, mx = 0.0, res = 0.0, yy = 0.0, yd = 0.0;
   for (int i = tid; i < nr; i += kThreads) {

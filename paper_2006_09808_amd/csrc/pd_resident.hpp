@@ -1,0 +1,441 @@
+// pd_resident.hpp - the iteration kept resident on chip for K iterations.
+//
+// A team of TEAM workgroups owns one slice pair of an NX x NY volume.  For
+// the whole launch each workgroup keeps in registers
+//   - its RT = NY/TEAM rows of chi (row phase), and
+//   - its CT = NX/TEAM columns of Yhat, F delta and D (column phase),
+// so the only memory traffic per iteration is the half-transformed field the
+// row and column phases hand each other through the exchange buffer.  Each
+// iteration is one column phase (forward column FFT, frequency-domain dual
+// prox, inverse column FFT) and one row phase (inverse row FFT, soft
+// threshold, over-relaxation, forward row FFT) of the PD pseudocode
+// (Sec. II-A), with a team barrier after each phase.
+//
+// Workgroup b of the launch runs on XCD b mod 8 (the dispatcher hands
+// workgroups to the XCDs round robin), and the kernel groups the workgroups of
+// one XCD into teams, so a team's exchange traffic stays in that XCD's L2,
+// the coherence point of all its CUs.  Team barriers then only need each
+// wave's stores to have reached L2 (s_waitcnt) and the exchange loads to skip
+// the CU's L1 (sc1), with no L2 write-back.  Each workgroup checks the XCD it
+// actually runs on (HW_REG_XCC_ID) in a first team barrier; if any member of
+// a team is elsewhere, that team uses agent-scope release/acquire fences
+// (L2 write-back and invalidate) for every barrier instead, which is correct
+// wherever its workgroups run.  The launch is cooperative (every workgroup
+// co-resident); a bounded spin turns a barrier that never completes into an
+// abort flag that every workgroup sees, so the grid always drains.
+#pragma once
+
+#include "pd_kern_impl.hpp"
+
+namespace pdk {
+
+constexpr unsigned kSpinLimit = 1u << 22;
+
+// Raw buffer access: a per-thread 32-bit byte offset plus a wave-uniform one
+// (an SGPR), so the strided exchange-buffer addresses cost no vector
+// registers across the iteration loop.  Out-of-range offsets read 0 and drop
+// writes (the resource carries the buffer size).
+typedef unsigned u32x2_t __attribute__((__vector_size__(2 * sizeof(unsigned))));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+// Exchange loads are device-scope (sc1): they skip the CU's L1, whose lines
+// may predate another member's store, and read the L2.
+__device__ __forceinline__ cpx<float> buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(cpx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 16));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, cpx<float> v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
+}
+
+// Element (s, j + r N/Q) of a pass with radix Q: per-thread part (s, j) and
+// the uniform part r.  Rows layout: element n of row s at s*ld + n; columns
+// layout: element n of column s at n*ld + s.
+template <typename F, int Q, bool COLS, int N, int LD>
+struct ExAddr {
+  static __device__ __forceinline__ bool voff(int tid, int q, int s0, unsigned& v) {
+    int w = tid + q * F::kNT, s, j;
+    F::template coords<Q>(w, s, j);
+    if constexpr (COLS) v = (unsigned)((j * LD + s0 + s) * 8);
+    else v = (unsigned)(((s0 + s) * LD + j) * 8);
+    return F::template nbutter<Q>() % F::kNT == 0 || w < F::template nbutter<Q>();
+  }
+  static constexpr unsigned soff(int r) {
+    return COLS ? (unsigned)(r * (N / Q) * LD * 8) : (unsigned)(r * (N / Q) * 8);
+  }
+};
+
+// Arrive at a team barrier and wait for `target` arrivals in total; thread 0
+// only.  Returns false once the spin limit is hit or another workgroup aborted.
+__device__ __forceinline__ bool arrive_wait(unsigned* cnt, unsigned add, unsigned target, unsigned mask,
+                                            unsigned* seen, int* abort_flag) {
+  unsigned v = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
+  unsigned spins = 0;
+  while ((v & mask) < target) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  *seen = v;
+  return true;
+}
+
+// Team barrier: every earlier exchange store of every member is visible to
+// every later exchange load (sc1) of every member.  `fenced` selects the
+// agent-scope protocol (members on different XCDs).  Returns false in all
+// threads once any workgroup has aborted.
+__device__ __forceinline__ bool team_barrier(unsigned* cnt, unsigned target, int* abort_flag, int* lds_flag,
+                                             bool fenced) {
+  // this wave's stores have reached L2 (the compiler may not move memory
+  // operations across the signal fences)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    unsigned seen;
+    int ok = arrive_wait(cnt, 1u, target, 0xffffffffu, &seen, abort_flag) ? 1 : 0;
+    if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *lds_flag = ok;
+  }
+  __syncthreads();
+  return *lds_flag != 0;
+}
+
+template <int NX, int NY, int TEAM, int NT>
+struct Resident {
+  static constexpr int RT = NY / TEAM;   // rows per workgroup (row phase)
+  static constexpr int CT = NX / TEAM;   // columns per workgroup (column phase)
+  using FR = Fft<float, NX, RT, NT, false>;
+  using FC = Fft<float, NY, CT, NT, true>;
+  static constexpr int LDS = FR::LDS_ELEMS > FC::LDS_ELEMS ? FR::LDS_ELEMS : FC::LDS_ELEMS;
+  // row phase: inverse first radix QI (exchange in), inverse last radix QO
+  // (chi state; forward first radix)
+  static constexpr int QI = FR::template QF<+1>();
+  static constexpr int QO = FR::template QL<+1>();
+  // column phase: forward first radix QA (exchange in/out), forward last
+  // radix QB (dual state)
+  static constexpr int QA = FC::template QF<-1>();
+  static constexpr int QB = FC::template QL<-1>();
+  static constexpr int NQI = FR::template nq<QI>();
+  static constexpr int NQO = FR::template nq<QO>();
+  static constexpr int NQA = FC::template nq<QA>();
+  static constexpr int NQB = FC::template nq<QB>();
+};
+
+// counters: 2 per team (barrier arrivals, placement check), zeroed per launch.
+template <int NX, int NY, int TEAM, int NT>
+__global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
+                                                 int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
+                                                 int* __restrict__ abort_flag, int nteams, int force_fenced) {
+  using R = Resident<NX, NY, TEAM, NT>;
+  using FR = typename R::FR;
+  using FC = typename R::FC;
+  using T = float;
+  __shared__ cpx<T> lds[R::LDS];
+  __shared__ cpx<T> dh_s[R::CT * NY];        // F delta of this workgroup's columns, [row][column]
+  __shared__ int lds_flag;
+
+  const int tid = threadIdx.x;
+  // team t = (workgroup's team within its XCD) * 8 + XCD
+  const int b = (int)blockIdx.x;
+  const int xcd = b % kXcds;
+  const int local = b / kXcds;
+  const int t = (local / TEAM) * kXcds + xcd;
+  if (t >= nteams) return;                    // padding team of the last XCD round
+  int slot, pair, m;
+  find_work_b(ranges, nranges, TEAM, t * TEAM + (local % TEAM), slot, pair, m);
+  const Vol& V = vols[slot];
+  if (ctl[slot].stop || V.iters <= 0 || V.check_only) return;   // uniform over the team
+  const int iters = V.iters;
+  const bool check = V.check_last != 0;
+  const bool final_step = V.final_it == iters - 1;
+  unsigned* cnt = counters + 2 * t;
+
+  // placement check: one arrival per member, +0x10000 if it is not on XCD t mod 8
+  if (tid == 0) {
+    const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
+    const unsigned add = 1u + ((here == (unsigned)xcd && !force_fenced) ? 0u : 0x10000u);
+    unsigned seen = 0;
+    int fen = 1;
+    if (arrive_wait(counters + 2 * t + 1, add, TEAM, 0xffffu, &seen, abort_flag)) fen = (seen >> 16) != 0;
+    else fen = -1;
+    lds_flag = fen;
+  }
+  __syncthreads();
+  if (lds_flag < 0) return;                   // aborted before any state was touched
+  const bool fenced = lds_flag != 0;
+
+  const size_t plane = (size_t)NX * NY;
+  const size_t base = (size_t)pair * plane;
+  const int r0 = m * R::RT;
+  const int c0 = m * R::CT;
+  const cpx<T>* __restrict__ twx = (const cpx<T>*)V.twx;
+  const cpx<T>* __restrict__ twy = (const cpx<T>*)V.twy;
+  cpx<T>* __restrict__ ex = (cpx<T>*)V.ex + base;
+  cpx<T>* __restrict__ ex2 = (cpx<T>*)V.ex2 + base;
+  cpx<T>* __restrict__ chi_g = (cpx<T>*)V.chi + base;
+  cpx<T>* __restrict__ yh_g = (cpx<T>*)V.yhat + base;
+  const cpx<T>* __restrict__ dh_g = (const cpx<T>*)V.dhat + base;
+  const T* __restrict__ dtab = (const T*)V.dtab;
+  const T tau = (T)V.tau, tl = (T)(V.tau * V.lam), theta = (T)V.theta;
+  const T sig = (T)V.sigma, inv1ps = (T)(1.0 / (1.0 + V.sigma));
+  const T invN = (T)(1.0 / ((double)NX * (double)NY));
+  const bool pad_imag = V.half_last && pair == V.P - 1;
+
+  // ---- resident state ----
+  cpx<T> chi[R::NQO][R::QO];                 // rows r0.., inverse-last-pass positions
+  cpx<T> yh[R::NQB][R::QB];                  // columns c0.., forward-last-pass positions
+  T dk[R::NQB][R::QB];
+#pragma unroll
+  for (int q = 0; q < R::NQO; ++q)
+#pragma unroll
+    for (int r = 0; r < R::QO; ++r) {
+      int s, n;
+      if (FR::template pos<R::QO>(tid, q, r, s, n)) chi[q][r] = chi_g[(unsigned)((r0 + s) * NX + n)];
+    }
+#pragma unroll
+  for (int q = 0; q < R::NQB; ++q)
+#pragma unroll
+    for (int r = 0; r < R::QB; ++r) {
+      int s, n;
+      if (FC::template pos<R::QB>(tid, q, r, s, n)) {
+        const unsigned o = (unsigned)(n * NX + c0 + s);
+        yh[q][r] = yh_g[o];
+        dh_s[n * R::CT + s] = dh_g[o];
+        dk[q][r] = dtab[o];
+      }
+    }
+
+  // exchange-buffer resources of this pair (the whole [ny][nx] plane)
+  const __amdgpu_buffer_rsrc_t rex = buf_rsrc(ex, (unsigned)(plane * sizeof(cpx<T>)));
+  const __amdgpu_buffer_rsrc_t rex2 = buf_rsrc(ex2, (unsigned)(plane * sizeof(cpx<T>)));
+  using AC = ExAddr<FC, R::QA, true, NY, NX>;    // column phase, forward first / inverse last pass
+  using AR = ExAddr<FR, R::QI, false, NX, NX>;   // row phase, inverse first / forward last pass
+
+  unsigned phase = 0;
+  bool ok = true;
+  double acc_r[2] = {0.0, 0.0};
+  for (int it = 0; it < iters && ok; ++it) {
+    const bool last = it == iters - 1;
+    // ---------------- column phase ----------------
+    {
+      cpx<T> a[R::NQA][R::QA];
+      cpx<T> b[R::NQB][R::QB];
+#pragma unroll
+      for (int q = 0; q < R::NQA; ++q) {
+        unsigned v;
+        if (AC::voff(tid, q, c0, v)) {
+#pragma unroll
+          for (int r = 0; r < R::QA; ++r) a[q][r] = buf_ld(rex, v, AC::soff(r));
+        }
+      }
+      FC::template run<-1>(a, b, lds, twy, tid);
+#pragma unroll
+      for (int q = 0; q < R::NQB; ++q)
+#pragma unroll
+        for (int r = 0; r < R::QB; ++r) {
+          int s, n;
+          if (FC::template pos<R::QB>(tid, q, r, s, n)) {
+            T d = dk[q][r];
+            cpx<T> y = yh[q][r], e = dh_s[n * R::CT + s];
+            cpx<T> yn = mk((y.x + sig * (d * b[q][r].x - e.x)) * inv1ps,
+                           (y.y + sig * (d * b[q][r].y - e.y)) * inv1ps);
+            yh[q][r] = yn;
+            T dn = d * invN;
+            b[q][r] = mk(dn * yn.x, dn * yn.y);
+          }
+        }
+      FC::sync_before_reuse();
+      FC::template run<+1>(b, a, lds, twy, tid);
+#pragma unroll
+      for (int q = 0; q < R::NQA; ++q) {
+        unsigned v;
+        if (AC::voff(tid, q, c0, v)) {
+#pragma unroll
+          for (int r = 0; r < R::QA; ++r) buf_st(rex, v, AC::soff(r), a[q][r]);
+        }
+      }
+    }
+    ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced);
+    if (!ok) break;
+    // ---------------- row phase ----------------
+    {
+      cpx<T> a[R::NQI][R::QI];
+      cpx<T> b[R::NQO][R::QO];
+#pragma unroll
+      for (int q = 0; q < R::NQI; ++q) {
+        unsigned v;
+        if (AR::voff(tid, q, r0, v)) {
+#pragma unroll
+          for (int r = 0; r < R::QI; ++r) a[q][r] = buf_ld(rex, v, AR::soff(r));
+        }
+      }
+      FR::template run<+1>(a, b, lds, twx, tid);
+      const bool do_check = check && last;
+#pragma unroll
+      for (int q = 0; q < R::NQO; ++q)
+#pragma unroll
+        for (int r = 0; r < R::QO; ++r) {
+          int s, n;
+          if (FR::template pos<R::QO>(tid, q, r, s, n)) {
+            cpx<T> x0 = chi[q][r];
+            cpx<T> u = b[q][r];
+            T vx = x0.x - tau * u.x, vy = x0.y - tau * u.y;
+            T nx_ = vx - clampv(vx, -tl, tl);
+            T ny_ = vy - clampv(vy, -tl, tl);
+            if (pad_imag) {
+              ny_ = (T)0;
+              u.y = (T)0;
+            }
+            chi[q][r] = mk(nx_, ny_);
+            b[q][r] = mk(nx_ + theta * (nx_ - x0.x), ny_ + theta * (ny_ - x0.y));
+            if (do_check) {
+              acc_r[0] += fabs((double)nx_) + fabs((double)ny_);
+              acc_r[1] = fmax(acc_r[1], fmax(fabs((double)u.x), fabs((double)u.y)));
+            }
+          }
+        }
+      if (!(last && final_step)) {
+        FR::sync_before_reuse();
+        FR::template run<-1>(b, a, lds, twx, tid);
+#pragma unroll
+        for (int q = 0; q < R::NQI; ++q) {
+          unsigned v;
+          if (AR::voff(tid, q, r0, v)) {
+#pragma unroll
+            for (int r = 0; r < R::QI; ++r) buf_st(rex, v, AR::soff(r), a[q][r]);
+          }
+        }
+      }
+      if (do_check) {
+        block_reduce<2, 2, NT>(acc_r, tid);
+        if (tid == 0) {
+          double* out = V.part_row + ((size_t)pair * TEAM + m) * 2;
+          out[0] = acc_r[0];
+          out[1] = acc_r[1];
+        }
+        // chi is final for this launch: write it back now and transform it
+        // in place for the residual
+#pragma unroll
+        for (int q = 0; q < R::NQO; ++q)
+#pragma unroll
+          for (int r = 0; r < R::QO; ++r) {
+            int s, n;
+            if (FR::template pos<R::QO>(tid, q, r, s, n)) chi_g[(unsigned)((r0 + s) * NX + n)] = chi[q][r];
+          }
+        FR::sync_before_reuse();
+        FR::template run<-1>(chi, a, lds, twx, tid);
+#pragma unroll
+        for (int q = 0; q < R::NQI; ++q) {
+          unsigned v;
+          if (AR::voff(tid, q, r0, v)) {
+#pragma unroll
+            for (int r = 0; r < R::QI; ++r) buf_st(rex2, v, AR::soff(r), a[q][r]);
+          }
+        }
+      }
+    }
+    if (!last || check) {
+      ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced);
+      if (!ok) break;
+    }
+  }
+
+  if (ok && check) {
+    // residual of F chi against F delta, and the dual's norms, per workgroup
+    cpx<T> a[R::NQA][R::QA];
+    cpx<T> b[R::NQB][R::QB];
+#pragma unroll
+    for (int q = 0; q < R::NQA; ++q) {
+      unsigned v;
+      if (AC::voff(tid, q, c0, v)) {
+#pragma unroll
+        for (int r = 0; r < R::QA; ++r) a[q][r] = buf_ld(rex2, v, AC::soff(r));
+      }
+    }
+    FC::template run<-1>(a, b, lds, twy, tid);
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < R::NQB; ++q)
+#pragma unroll
+      for (int r = 0; r < R::QB; ++r) {
+        int s, n;
+        if (FC::template pos<R::QB>(tid, q, r, s, n)) {
+          T d = dk[q][r];
+          cpx<T> e = dh_s[n * R::CT + s], y = yh[q][r];
+          double rx = (double)(d * b[q][r].x - e.x), ry = (double)(d * b[q][r].y - e.y);
+          acc[0] += rx * rx + ry * ry;
+          acc[1] += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+          acc[2] += (double)y.x * (double)e.x + (double)y.y * (double)e.y;
+        }
+      }
+    block_reduce<3, 0, NT>(acc, tid);
+    if (tid == 0) {
+      double* out = V.part_col + ((size_t)pair * TEAM + m) * 3;
+      out[0] = acc[0];
+      out[1] = acc[1];
+      out[2] = acc[2];
+    }
+  }
+
+  // ---- write the state back (chi already written on a check) ----
+  if (!(ok && check)) {
+#pragma unroll
+    for (int q = 0; q < R::NQO; ++q)
+#pragma unroll
+      for (int r = 0; r < R::QO; ++r) {
+        int s, n;
+        if (FR::template pos<R::QO>(tid, q, r, s, n)) chi_g[(unsigned)((r0 + s) * NX + n)] = chi[q][r];
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < R::NQB; ++q)
+#pragma unroll
+    for (int r = 0; r < R::QB; ++r) {
+      int s, n;
+      if (FC::template pos<R::QB>(tid, q, r, s, n)) yh_g[(unsigned)(n * NX + c0 + s)] = yh[q][r];
+    }
+}
+
+// Cooperative launch of `grid` workgroups (a multiple of TEAM).  Returns
+// hipErrorCooperativeLaunchTooLarge if they cannot all be co-resident.
+template <int NX, int NY, int TEAM, int NT>
+hipError_t launch_resident_t(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                             unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {
+  const int rounds = (nteams + kXcds - 1) / kXcds;
+  const int grid = rounds * kXcds * TEAM;
+  void* args[] = {(void*)&vols,     (void*)&ranges,     (void*)&nranges, (void*)&ctl,
+                  (void*)&counters, (void*)&abort_flag, (void*)&nteams,  (void*)&fenced};
+  return hipLaunchCooperativeKernel((const void*)k_resident<NX, NY, TEAM, NT>, dim3(grid), dim3(NT), args, 0, st);
+}
+
+template <int NX, int NY, int TEAM, int NT>
+int resident_max_teams_t() {
+  int per_cu = 0, dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_resident<NX, NY, TEAM, NT>, NT, 0) !=
+      hipSuccess)
+    return 0;
+  int teams = per_cu * ncu / TEAM;
+  return teams - teams % kXcds;
+}
+
+}  // namespace pdk
+
+// Defines the resident launcher of the square N x N slice shape.
+#define PD_INSTANTIATE_RESIDENT(N, TEAM, NT)                                                             \
+  namespace pdk {                                                                                        \
+  hipError_t launch_resident_##N(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl, \
+                                 unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {     \
+    return launch_resident_t<N, N, TEAM, NT>(nteams, vols, ranges, nranges, ctl, counters, abort_flag,   \
+                                             fenced, st);                                                 \
+  }                                                                                                      \
+  int resident_team_##N() { return TEAM; }                                                              \
+  int resident_max_teams_##N() { return resident_max_teams_t<N, N, TEAM, NT>(); }                       \
+  }

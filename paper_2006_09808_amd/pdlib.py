@@ -18,8 +18,8 @@ PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET = -1, -2, -3, -4
 PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE = -5, -6, -7, -8, -9
 PD_FP32, PD_FP64 = 0, 1
 PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY = 0, 1
-PD_FLAG_TIME_KERNELS = 1
-KIND_COLUMN, KIND_ROW = 0, 1
+PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE = 1, 2, 4
+KIND_COLUMN, KIND_ROW, KIND_RESIDENT = 0, 1, 2
 
 SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
@@ -77,7 +77,8 @@ def load_library(path=None):
     lib.pd_apply_kernel.argtypes = [c.c_void_p, c.POINTER(PdRequest)]
     lib.pd_now.argtypes = []
     lib.pd_now.restype = c.c_double
-    lib.pd_kernel_time.argtypes = [c.c_void_p, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double)]
+    lib.pd_kernel_time.argtypes = [c.c_void_p, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double),
+                                   c.POINTER(c.c_double)]
     lib.pd_kernel_time_reset.argtypes = [c.c_void_p]
     lib.pd_arena_usage.argtypes = [c.c_void_p, c.POINTER(c.c_size_t), c.POINTER(c.c_int), c.POINTER(c.c_int)]
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
@@ -157,7 +158,8 @@ class Solver:
     iterates every admitted request together (continuous batching)."""
 
     def __init__(self, arena_bytes=1 << 30, device=0, max_slots=0, precision="fp32",
-                 step_iters=0, time_kernels=False, stream=None, arena=None):
+                 step_iters=0, time_kernels=False, resident=True, fenced_exchange=False, stream=None,
+                 arena=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -175,7 +177,8 @@ class Solver:
         cfg.max_slots = int(max_slots)
         cfg.precision = self.precision
         cfg.step_iters = int(step_iters)
-        cfg.flags = PD_FLAG_TIME_KERNELS if time_kernels else 0
+        cfg.flags = ((PD_FLAG_TIME_KERNELS if time_kernels else 0) | (0 if resident else PD_FLAG_NO_RESIDENT)
+                     | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0))
         self._ctx = ctypes.c_void_p()
         st = self.lib.pd_create(ctypes.byref(cfg), ctypes.byref(self._ctx))
         if st != PD_OK:
@@ -252,12 +255,15 @@ class Solver:
 
     # -- introspection -----------------------------------------------------
     def kernel_time(self, kind):
+        """(launches, summed HIP-event ms, summed iterations x slice-pair points)
+        of one kernel class (KIND_COLUMN, KIND_ROW, KIND_RESIDENT)."""
         n = ctypes.c_int64(0)
         ms = ctypes.c_double(0.0)
-        st = self.lib.pd_kernel_time(self._ctx, int(kind), ctypes.byref(n), ctypes.byref(ms))
+        pts = ctypes.c_double(0.0)
+        st = self.lib.pd_kernel_time(self._ctx, int(kind), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(pts))
         if st != PD_OK:
             raise PdError(st, "pd_kernel_time")
-        return int(n.value), float(ms.value)
+        return int(n.value), float(ms.value), float(pts.value)
 
     def kernel_time_reset(self):
         self.lib.pd_kernel_time_reset(self._ctx)

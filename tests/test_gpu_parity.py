@@ -36,6 +36,35 @@ def solver(torch_mod):
     s.close()
 
 
+@pytest.fixture(scope="module")
+def solver_two(torch_mod):
+    """Same library, resident kernel disabled: two launches per iteration."""
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0, resident=False)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def solver_fenced(torch_mod):
+    """Resident kernel exchanging through agent-scope release/acquire fences
+    (the protocol used when a team's workgroups are not on one XCD)."""
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0, fenced_exchange=True, step_iters=11)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def solver_short(torch_mod):
+    """Resident kernel with 7-iteration steps: state saved and restored
+    between launches, gap checks at step ends."""
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0, step_iters=7)
+    yield s
+    s.close()
+
+
 def make_case(seed, nz, ny, nx, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), **params):
     w = pd_inputs.random_stack(seed, nz, ny, nx, **params)
     w.b0, w.voxel = b0, voxel
@@ -90,12 +119,16 @@ SOLVE_CASES = [
     (5, 5, 48, 32, dict(lam=2e-3, max_iter=50, theta=0.5, tau=1.0, sigma=1.2)),
     (6, 4, 128, 128, dict(lam=1e-3, max_iter=100)),
     (7, 3, 256, 256, dict(lam=1e-3, max_iter=40)),
+    (8, 5, 64, 64, dict(lam=1e-3, max_iter=45, b0=(0.6, 0.8, 0.0), theta=0.7)),
 ]
 
 
+@pytest.mark.parametrize("path", ["default", "two_launch", "short_steps", "fenced"])
 @pytest.mark.parametrize("seed,nz,ny,nx,params", SOLVE_CASES)
-def test_fixed_iterations_match_oracle(solver, torch_mod, seed, nz, ny, nx, params):
-    _say("solve seed=%d nz=%d ny=%d nx=%d %s" % (seed, nz, ny, nx, params))
+def test_fixed_iterations_match_oracle(request, torch_mod, path, seed, nz, ny, nx, params):
+    solver = request.getfixturevalue({"default": "solver", "two_launch": "solver_two",
+                                      "short_steps": "solver_short", "fenced": "solver_fenced"}[path])
+    _say("solve [%s] seed=%d nz=%d ny=%d nx=%d %s" % (path, seed, nz, ny, nx, params))
     p = dict(params)
     b0 = p.pop("b0", (0.0, 1.0, 0.0))
     vox = p.pop("voxel", (1.0, 1.0))
@@ -125,8 +158,12 @@ def test_config1_plain_64x64(solver, torch_mod):
     assert info["iterations"] == 200
 
 
-def test_gap_report_matches_oracle(solver, torch_mod):
-    w, delta = make_case(11, 2, 64, 64, lam=1e-3, max_iter=40, gap_tol=1e-12, check_every=10)
+@pytest.mark.parametrize("path", ["default", "two_launch", "fenced"])
+@pytest.mark.parametrize("shape", [(2, 64, 64), (3, 128, 128), (2, 96, 64), (2, 256, 256)])
+def test_gap_report_matches_oracle(request, torch_mod, path, shape):
+    solver = request.getfixturevalue({"default": "solver", "two_launch": "solver_two",
+                                      "fenced": "solver_fenced"}[path])
+    w, delta = make_case(11, *shape, lam=1e-3, max_iter=40, gap_tol=1e-12, check_every=10)
     sp = w.solver_params()
     _say("gap report 64x64x2, 40 iterations, checks every 10")
     hist = []
@@ -141,9 +178,10 @@ def test_gap_report_matches_oracle(solver, torch_mod):
     assert rel_l2(got, ref) <= REL_TOL
 
 
-def test_identity_kernel_tolerance_stop(solver, torch_mod):
+@pytest.mark.parametrize("shape", [(3, 32, 64), (3, 64, 64), (2, 128, 128)])
+def test_identity_kernel_tolerance_stop(solver, torch_mod, shape):
     rng = np.random.default_rng(21)
-    delta = rng.normal(size=(3, 32, 64)).astype(np.float32)
+    delta = rng.normal(size=shape).astype(np.float32)
     sp = dict(lam=0.2, tau=0.9, sigma=0.9, theta=1.0, max_iter=400, gap_tol=1e-5, check_every=5,
               kernel="identity")
     _say("identity kernel, gap_tol 1e-5")
@@ -256,3 +294,33 @@ def test_batched_config_full_size_sampled(solver, torch_mod):
         err = rel_l2(got[z:z + 1], ref)
         _say("  slice %d relL2 %.3e max-abs %.3e" % (z, err, np.abs(got[z] - ref[0]).max()))
         assert err <= REL_TOL
+
+
+def test_resident_batch_split_across_launches(solver, torch_mod):
+    """66 slices of 256x256 (33 pairs) exceed one co-resident launch (32 pairs
+    of 8 workgroups on 256 CUs), so one volume spans two launches."""
+    w, delta = make_case(61, 66, 256, 256, lam=1e-3, max_iter=30)
+    sp = w.solver_params()
+    _say("256x256x66, 30 iterations (two resident launches per step)")
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    assert info["iterations"] == 30
+    for z in (0, 63, 64, 65):
+        ref, _ = oracle.solve(delta[z:z + 1].astype(np.float64), **sp)
+        err = rel_l2(got[z:z + 1], ref)
+        _say("  slice %d relL2 %.3e" % (z, err))
+        assert err <= REL_TOL
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_resident_protocols_and_two_launch_path_agree(solver, solver_two, solver_fenced, torch_mod, n):
+    """Same arithmetic in the same order: the XCD-local and fenced exchange
+    give bitwise equal results; the two-launch path agrees to rounding."""
+    w, delta = make_case(71, 6, n, n, lam=1e-3, max_iter=44, gap_tol=1e-9, check_every=22)
+    sp = w.solver_params()
+    a, ia = gpu_solve(solver, torch_mod, delta, **sp)
+    f, iff = gpu_solve(solver_fenced, torch_mod, delta, **sp)
+    b, ib = gpu_solve(solver_two, torch_mod, delta, **sp)
+    assert ia["iterations"] == ib["iterations"] == iff["iterations"] == 44
+    np.testing.assert_array_equal(a, f)
+    assert rel_l2(a, b) <= 1e-5
+    assert ia["primal"] == pytest.approx(ib["primal"], rel=1e-5)
