@@ -47,6 +47,10 @@ def parse():
     ap.add_argument("--no-per-slice", action="store_true")
     ap.add_argument("--cpu-sample-slices", type=int, default=16)
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the Poisson serving run (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-arena-gb", type=float, default=64.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only time a plain device copy of BYTES bytes (the reference kernel for "
                          "scaling hardware byte counters) and exit")
@@ -92,6 +96,40 @@ def measured_traffic(kernel):
         if rec.get("kernel") == kernel and rec.get("sources_sha256_16") == h.hexdigest()[:16]:
             return rec["read_bytes"] + rec["write_bytes"]
     return None
+
+
+def serving(rate, seconds, arena_gb):
+    """Open-loop Poisson arrivals: in-plane size uniform over 128^2, 192^2,
+    256^2, 384^2, 16-64 slices, gap tolerance 1e-5 (FP64 gap every 10
+    iterations), cap 1000 iterations, admission under an arena of arena_gb.
+    Each request is a window of slices of a seeded phantom volume of its
+    size, field maps made on the GPU with the library's forward operator."""
+    import torch
+    import pd_inputs
+    import paper_2006_09808_amd as pd
+    from paper_2006_09808_amd import serve
+
+    dev = torch.device("cuda", 0)
+    sched = pd_inputs.serving_schedule(rate=rate, duration=seconds)
+    with pd.Solver(arena_bytes=int(arena_gb * (1 << 30)), device=0) as s:
+        base = {}
+        for i, n in enumerate(pd_inputs.SERVING_SIZES):
+            w = pd_inputs.serving_request(5000 + 100 * i, n, 64)
+            chi_t = torch.from_numpy(w.chi_true.astype(np.float32)).to(dev)
+            field = s.apply_kernel(chi_t).cpu().numpy().astype(np.float64)
+            base[n] = torch.from_numpy(pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)).to(dev)
+        params = dict(lam=1e-3, tau=1.4, sigma=1.4, theta=1.0, max_iter=1000, gap_tol=1e-5, check_every=10)
+        reqs = []
+        for (t, n, nz, seed) in sched:
+            off = seed % (64 - nz + 1)
+            d = base[n][off:off + nz]
+            reqs.append(serve.Request(t, d, torch.empty_like(d), params))
+        torch.cuda.synchronize()
+        summary = serve.run_open_loop(s, reqs)
+    summary.update({"arrival_rate_per_s": rate, "duration_s": seconds, "arena_GB": arena_gb,
+                    "sizes": list(pd_inputs.SERVING_SIZES), "slices": [16, 64],
+                    "gap_tol": 1e-5, "max_iter": 1000})
+    return summary
 
 
 def cpu_baseline(w, nslices, iters):
@@ -216,6 +254,8 @@ def main():
                      "kernels": kernels},
         "rel_gap": info["rel_gap"],
     }
+    if a.serve_seconds > 0:
+        out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_slices, a.cpu_sample_iters)
     print(json.dumps(out), flush=True)

@@ -28,6 +28,7 @@ PD_DECL(512)
   int resident_max_teams_##N();
 PD_DECL_RES(64)
 PD_DECL_RES(128)
+PD_DECL_RES(192)
 PD_DECL_RES(256)
 #undef PD_DECL_RES
 
@@ -35,6 +36,7 @@ int resident_team(int n) {
   switch (n) {
     case 64: return resident_team_64();
     case 128: return resident_team_128();
+    case 192: return resident_team_192();
     case 256: return resident_team_256();
     default: return 0;
   }
@@ -44,6 +46,7 @@ int resident_max_teams(int n) {
   switch (n) {
     case 64: return resident_max_teams_64();
     case 128: return resident_max_teams_128();
+    case 192: return resident_max_teams_192();
     case 256: return resident_max_teams_256();
     default: return 0;
   }
@@ -54,6 +57,7 @@ hipError_t launch_resident(int n, int nteams, const Vol* vols, const Range* rang
   switch (n) {
     case 64: return launch_resident_64(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
     case 128: return launch_resident_128(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
+    case 192: return launch_resident_192(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
     case 256: return launch_resident_256(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
     default: return hipErrorInvalidValue;
   }

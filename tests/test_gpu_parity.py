@@ -120,6 +120,7 @@ SOLVE_CASES = [
     (6, 4, 128, 128, dict(lam=1e-3, max_iter=100)),
     (7, 3, 256, 256, dict(lam=1e-3, max_iter=40)),
     (8, 5, 64, 64, dict(lam=1e-3, max_iter=45, b0=(0.6, 0.8, 0.0), theta=0.7)),
+    (9, 3, 192, 192, dict(lam=1e-3, max_iter=50)),
 ]
 
 
@@ -311,7 +312,7 @@ def test_resident_batch_split_across_launches(solver, torch_mod):
         assert err <= REL_TOL
 
 
-@pytest.mark.parametrize("n", [64, 128, 256])
+@pytest.mark.parametrize("n", [64, 128, 192, 256])
 def test_resident_protocols_and_two_launch_path_agree(solver, solver_two, solver_fenced, torch_mod, n):
     """Same arithmetic in the same order: the XCD-local and fenced exchange
     give bitwise equal results; the two-launch path agrees to rounding."""
