@@ -60,10 +60,12 @@ enum {
                                 HIP events on the context stream (pd_kernel_time) */
   PD_FLAG_NO_RESIDENT = 2,   /* never use the resident multi-iteration kernel:
                                 two launches per iteration for every shape     */
-  PD_FLAG_FENCED_EXCHANGE = 4 /* resident kernel: always exchange between the
+  PD_FLAG_FENCED_EXCHANGE = 4, /* resident kernel: always exchange between the
                                 workgroups of a team with agent-scope
                                 release/acquire (L2 write-back), even when
                                 they share an XCD                              */
+  PD_FLAG_NO_GRAPHS = 8      /* never replay a step of the two-launch path from
+                                a captured HIP graph                           */
 };
 
 typedef struct pd_ctx pd_ctx;     /* opaque, library-owned */
@@ -164,6 +166,10 @@ double pd_now(void);
  * iterations of square slices kept on chip).  pd_kernel_time_reset clears all. */
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
+
+/* Scheduling steps of the two-launch path captured into HIP graphs, and
+ * steps replayed from one, since pd_create. */
+pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays);
 
 /* Bytes of arena currently in use and the number of resident requests. */
 pd_status pd_arena_usage(pd_ctx* c, size_t* used, int* resident, int* queued);

@@ -27,6 +27,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -38,6 +39,7 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultSlots = 256;
 constexpr int kDefaultStep = 100;
 constexpr int kMaxStep = 1 << 20;
+constexpr int kMaxGraphs = 32;
 constexpr int kMaxCounters = 4096;   // team barrier counters per resident launch (2 per team)
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -311,6 +313,16 @@ struct pd_ctx {
   Ctl* h_ctl = nullptr;
   int* h_slots = nullptr;
   Range* h_ranges = nullptr;
+
+  // captured step graphs of the two-launch path, keyed by launch plan
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int seen = 0;
+    uint64_t last_use = 0;
+  };
+  std::map<std::string, GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  int64_t graph_replays = 0, graph_captures = 0;
 
   // kernel timing
   bool time_kernels = false;
@@ -685,42 +697,94 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
     });
     if (e != hipSuccess) return e;
   }
-  // two-launch path
+  // two-launch path (K iterations of column and row launches), then the
+  // checks: replayed from a captured graph when the same plan recurs
   bool any_two = false;
   for (auto& L : launches) any_two |= !L.resident;
-  if (any_two) {
-    for (int it = 0; it < K; ++it) {
-      for (auto& L : launches) {
-        if (L.resident) continue;
-        const Range* rrow = c->d_ranges + L.row_off;
-        const Range* rcol = c->d_ranges + L.col_off;
-        double pts = (double)L.npairs * L.nx * L.ny;
-        e = timed(0, pts, [&] {
-          return launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, it,
-                            c->precision, c->stream);
-        });
-        if (e != hipSuccess) return e;
-        e = timed(1, pts, [&] {
-          return launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl, it,
-                            c->precision, c->stream);
-        });
-        if (e != hipSuccess) return e;
+  auto enqueue_rest = [&](bool with_events) -> hipError_t {
+    hipError_t r = hipSuccess;
+    if (any_two) {
+      for (int it = 0; it < K; ++it) {
+        for (auto& L : launches) {
+          if (L.resident) continue;
+          const Range* rrow = c->d_ranges + L.row_off;
+          const Range* rcol = c->d_ranges + L.col_off;
+          double pts = (double)L.npairs * L.nx * L.ny;
+          auto col = [&] {
+            return launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                              it, c->precision, c->stream);
+          };
+          auto row = [&] {
+            return launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                              it, c->precision, c->stream);
+          };
+          r = with_events ? timed(0, pts, col) : col();
+          if (r != hipSuccess) return r;
+          r = with_events ? timed(1, pts, row) : row();
+          if (r != hipSuccess) return r;
+        }
+      }
+      if (any_check) {
+        for (auto& L : launches) {
+          if (L.resident) continue;
+          const Range* rcol = c->d_ranges + L.col_off;
+          r = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                         K - 1, c->precision, c->stream);
+          if (r != hipSuccess) return r;
+        }
       }
     }
     if (any_check) {
-      for (auto& L : launches) {
-        if (L.resident) continue;
-        const Range* rcol = c->d_ranges + L.col_off;
-        e = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl, K - 1,
-                       c->precision, c->stream);
-        if (e != hipSuccess) return e;
+      // check-only volumes have iters == 1: their reduction runs at it == 0 == K - 1
+      r = launch_reduce(nslot_list, c->d_vols, c->d_slots, c->d_ctl, K - 1, c->precision, c->stream);
+      if (r != hipSuccess) return r;
+    }
+    return r;
+  };
+  bool use_graph = any_two && !c->time_kernels && !(c->cfg.flags & PD_FLAG_NO_GRAPHS);
+  if (use_graph) {
+    std::string sig = std::to_string(K) + (any_check ? "c" : "n") + std::to_string(nslot_list) + ":" +
+                      std::to_string(c->precision);
+    for (auto& L : launches) {
+      if (L.resident) continue;
+      sig += "|" + std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
+             std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
+             std::to_string(L.row_off) + "," + std::to_string(L.col_off);
+    }
+    auto& G = c->graphs[sig];
+    G.last_use = ++c->graph_clock;
+    if (!G.exec && ++G.seen >= 2) {
+      // a plan seen before: capture it once, replay it from now on
+      hipGraph_t g = nullptr;
+      e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      hipError_t ecap = enqueue_rest(false);
+      e = hipStreamEndCapture(c->stream, &g);
+      if (ecap != hipSuccess) e = ecap;
+      if (e == hipSuccess) e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return e;
+      c->graph_captures++;
+      if (c->graphs.size() > (size_t)kMaxGraphs) {   // evict the least recently used plan
+        auto victim = c->graphs.end();
+        for (auto it2 = c->graphs.begin(); it2 != c->graphs.end(); ++it2)
+          if (it2->second.exec && &it2->second != &G &&
+              (victim == c->graphs.end() || it2->second.last_use < victim->second.last_use))
+            victim = it2;
+        if (victim != c->graphs.end()) {
+          (void)hipGraphExecDestroy(victim->second.exec);
+          c->graphs.erase(victim);
+        }
       }
     }
-  }
-  if (any_check) {
-    // check-only volumes have iters == 1: their reduction runs at it == 0 == K - 1
-    e = launch_reduce(nslot_list, c->d_vols, c->d_slots, c->d_ctl, K - 1, c->precision, c->stream);
-    if (e != hipSuccess) return e;
+    if (G.exec) {
+      if ((e = hipGraphLaunch(G.exec, c->stream)) != hipSuccess) return e;
+      c->graph_replays++;
+    } else if ((e = enqueue_rest(false)) != hipSuccess) {
+      return e;
+    }
+  } else if ((e = enqueue_rest(c->time_kernels)) != hipSuccess) {
+    return e;
   }
   if ((e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl) * c->nslots, hipMemcpyDeviceToHost, c->stream)) !=
       hipSuccess)
@@ -1044,6 +1108,8 @@ pd_status pd_destroy(pd_ctx* c) {
     c->cv_done.notify_all();
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& g : c->graphs)
+    if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
   if (c->h_vols) (void)hipHostFree(c->h_vols);
   if (c->h_ctl) (void)hipHostFree(c->h_ctl);
   if (c->h_slots) (void)hipHostFree(c->h_slots);
@@ -1143,6 +1209,14 @@ pd_status pd_kernel_time_reset(pd_ctx* c) {
     c->t_ms[k] = 0.0;
     c->t_points[k] = 0.0;
   }
+  return PD_OK;
+}
+
+pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays) {
+  if (!c) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> ex(c->exec_mu);
+  if (captures) *captures = c->graph_captures;
+  if (replays) *replays = c->graph_replays;
   return PD_OK;
 }
 

@@ -18,14 +18,14 @@ PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET = -1, -2, -3, -4
 PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE = -5, -6, -7, -8, -9
 PD_FP32, PD_FP64 = 0, 1
 PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY = 0, 1
-PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE = 1, 2, 4
+PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
 KIND_COLUMN, KIND_ROW, KIND_RESIDENT = 0, 1, 2
 
 SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",
            "pd_validate", "pd_kernel_norm", "pd_apply_kernel", "pd_now",
-           "pd_kernel_time", "pd_kernel_time_reset", "pd_arena_usage")
+           "pd_kernel_time", "pd_kernel_time_reset", "pd_graph_stats", "pd_arena_usage")
 
 
 class PdConfig(ctypes.Structure):
@@ -81,9 +81,10 @@ def load_library(path=None):
                                    c.POINTER(c.c_double)]
     lib.pd_kernel_time_reset.argtypes = [c.c_void_p]
     lib.pd_arena_usage.argtypes = [c.c_void_p, c.POINTER(c.c_size_t), c.POINTER(c.c_int), c.POINTER(c.c_int)]
+    lib.pd_graph_stats.argtypes = [c.c_void_p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
                  "pd_kernel_norm", "pd_apply_kernel", "pd_kernel_time", "pd_kernel_time_reset",
-                 "pd_arena_usage"):
+                 "pd_graph_stats", "pd_arena_usage"):
         getattr(lib, name).restype = c.c_int32
     if path is None:
         _lib = lib
@@ -158,8 +159,8 @@ class Solver:
     iterates every admitted request together (continuous batching)."""
 
     def __init__(self, arena_bytes=1 << 30, device=0, max_slots=0, precision="fp32",
-                 step_iters=0, time_kernels=False, resident=True, fenced_exchange=False, stream=None,
-                 arena=None):
+                 step_iters=0, time_kernels=False, resident=True, fenced_exchange=False, graphs=True,
+                 stream=None, arena=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -178,7 +179,7 @@ class Solver:
         cfg.precision = self.precision
         cfg.step_iters = int(step_iters)
         cfg.flags = ((PD_FLAG_TIME_KERNELS if time_kernels else 0) | (0 if resident else PD_FLAG_NO_RESIDENT)
-                     | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0))
+                     | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0) | (0 if graphs else PD_FLAG_NO_GRAPHS))
         self._ctx = ctypes.c_void_p()
         st = self.lib.pd_create(ctypes.byref(cfg), ctypes.byref(self._ctx))
         if st != PD_OK:
@@ -267,6 +268,15 @@ class Solver:
 
     def kernel_time_reset(self):
         self.lib.pd_kernel_time_reset(self._ctx)
+
+    def graph_stats(self):
+        """(steps captured into HIP graphs, steps replayed from one)."""
+        cap = ctypes.c_int64(0)
+        rep = ctypes.c_int64(0)
+        st = self.lib.pd_graph_stats(self._ctx, ctypes.byref(cap), ctypes.byref(rep))
+        if st != PD_OK:
+            raise PdError(st, "pd_graph_stats")
+        return int(cap.value), int(rep.value)
 
     def arena_usage(self):
         used = ctypes.c_size_t(0)

@@ -325,3 +325,27 @@ def test_resident_protocols_and_two_launch_path_agree(solver, solver_two, solver
     np.testing.assert_array_equal(a, f)
     assert rel_l2(a, b) <= 1e-5
     assert ia["primal"] == pytest.approx(ib["primal"], rel=1e-5)
+
+
+@pytest.mark.parametrize("gap_tol", [0.0, 1e-9])
+def test_graph_replay_equals_eager(torch_mod, gap_tol):
+    """Steps of the two-launch path replayed from a captured HIP graph give the
+    eager result bitwise, on every replay, with eager work in between."""
+    import paper_2006_09808_amd as pd
+    w, delta = make_case(81, 5, 96, 64, lam=1e-3, max_iter=300, gap_tol=gap_tol, check_every=50)
+    sp = w.solver_params()
+    with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=50, graphs=False) as eager:
+        ref, iref = gpu_solve(eager, torch_mod, delta, **sp)
+        assert eager.graph_stats() == (0, 0)
+    with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=50) as g:
+        for rep in range(3):
+            got, info = gpu_solve(g, torch_mod, delta, **sp)
+            np.testing.assert_array_equal(got, ref)
+            assert info["iterations"] == iref["iterations"] == 300
+            assert info["primal"] == iref["primal"]
+            # eager work between replays: the forward operator on the device
+            x = torch_mod.from_numpy(delta).to("cuda:0")
+            g.apply_kernel(x)
+        captures, replays = g.graph_stats()
+        _say("graph captures %d replays %d" % (captures, replays))
+        assert captures >= 1 and replays >= 8
