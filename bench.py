@@ -132,6 +132,8 @@ def serving(rate, seconds, arena_gb):
     dev = torch.device("cuda", 0)
     sched = pd_inputs.serving_schedule(rate=rate, duration=seconds)
     with pd.Solver(arena_bytes=int(arena_gb * (1 << 30)), device=0) as s:
+        for n in pd_inputs.SERVING_SIZES:
+            s.tune(n, n, 40, iters=20)
         base = {}
         for i, n in enumerate(pd_inputs.SERVING_SIZES):
             w = pd_inputs.serving_request(5000 + 100 * i, n, 64)
@@ -193,6 +195,9 @@ def main():
     sp = w.solver_params()
 
     with pd.Solver(arena_bytes=2 << 30, device=0, time_kernels=True) as s:
+        # autotune the kernel configuration of this shape on this device
+        tune_table = s.tune(NX, NY, NZ, iters=50)
+        tune_choice = s.tune_get(NX, NY)
         chi_true = torch.from_numpy(w.chi_true.astype(np.float32)).to(dev)
         field = s.apply_kernel(chi_true).cpu().numpy().astype(np.float64)
         delta = torch.from_numpy(pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)).to(dev)
@@ -287,6 +292,7 @@ def main():
             "speedup_batched": value / (vit / per_slice)},
         "roofline": roofline,
         "rel_gap": info["rel_gap"],
+        "autotune": {"choice": tune_choice, "timings": tune_table},
     }
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)

@@ -167,6 +167,35 @@ double pd_now(void);
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 
+/* One timed configuration of a slice shape (pd_tune). */
+typedef struct {
+  int nx, ny, nz, iters;  /* problem timed: nz slices of ny x nx, iters iterations   */
+  int path;               /* 0: resident kernel, 1: two launches per iteration       */
+  int variant;            /* resident: variant index; two-launch: -1                 */
+  int team, threads;      /* resident: workgroups per slice pair, threads per group  */
+  int rows, cols;         /* two-launch: rows per row-kernel workgroup, columns per
+                             column-kernel workgroup; resident: 0                    */
+  double ms;              /* best of three timed runs (HIP events), milliseconds      */
+} pd_tune_entry;
+
+/* Autotuner: time every kernel configuration of the nx x ny slice shape on a
+ * zero-filled volume of nz slices for `iters` iterations (resident-kernel
+ * variants for square FP32 shapes; row/column tile sizes of the two-launch
+ * kernels), then make the fastest of each path the context's choice for that
+ * shape.  Needs arena space like a solve of that size; blocks until done and
+ * runs between scheduling steps.  Up to max_entries timings are written to
+ * entries (may be NULL), their count to *n_entries.
+ * Errors: PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_BUDGET, PD_ERR_HIP. */
+pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
+                  int* n_entries);
+
+/* Set / read the context's configuration choice for the nx x ny shape
+ * (e.g. a choice saved from an earlier pd_tune).  variant < 0, rows <= 0 or
+ * cols <= 0 select the default of that knob; invalid values are rejected
+ * with PD_ERR_ARG. */
+pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols);
+pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols);
+
 /* Scheduling steps of the two-launch path captured into HIP graphs, and
  * steps replayed from one, since pd_create. */
 pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays);

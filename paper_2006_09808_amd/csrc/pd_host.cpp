@@ -107,15 +107,32 @@ void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
 }
 
 // work decomposition (must match the kernel instantiations)
-int rows_per_wg(int nx, int ny, int precision) {
-  if (precision == PD_FP64) return 8;
+int row_group_big(int nx) {   // the larger instantiated FP32 row group of length-nx rows
   int s = 8;
   while (s < 64 && 2 * s * nx <= 4096) s *= 2;
+  return s;
+}
+int rows_per_wg(int nx, int ny, int precision) {
+  if (precision == PD_FP64) return 8;
+  int s = row_group_big(nx);
   return (ny % s == 0) ? s : 8;
 }
 int cols_per_wg(int nx, int /*ny*/, int precision) {
   if (precision == PD_FP64) return 8;
   return (nx % 16 == 0) ? 16 : 8;
+}
+
+// instantiated tile sizes of the two-launch kernels (FP32): rows per row-kernel
+// workgroup in {8, default}, columns per column-kernel workgroup in {8, 16}
+bool rows_valid(int r, int nx, int ny, int precision) {
+  if (r <= 0 || ny % r) return false;
+  if (precision == PD_FP64) return r == 8;
+  return r == 8 || r == row_group_big(nx);
+}
+bool cols_valid(int cl, int nx, int precision) {
+  if (cl <= 0 || nx % cl) return false;
+  if (precision == PD_FP64) return cl == 8;
+  return cl == 8 || cl == 16;
 }
 
 struct Layout {
@@ -142,9 +159,10 @@ Layout layout_of(const pd_request& r, int precision) {
   L.off_dhat = o; o += L.field;
   L.off_ex = o; o += L.field;
   if (L.separate_ex2) { L.off_ex2 = o; o += L.field; } else { L.off_ex2 = L.off_ex; }
-  // gap partials: one entry per workgroup of either the two-launch kernels
-  // or the resident team (at most 16 workgroups per pair)
-  size_t pg = (size_t)std::max(std::max(L.row_groups, L.col_groups), 16);
+  // gap partials: one entry per workgroup of any tile choice of the
+  // two-launch kernels (8 rows or columns per workgroup at the least) or of
+  // any resident team (at most 32 workgroups per pair)
+  size_t pg = (size_t)std::max(std::max(r.ny / 8, r.nx / 8), 32);
   L.off_prow = o; o += align_up((size_t)L.P * pg * 2 * sizeof(double));
   L.off_pcol = o; o += align_up((size_t)L.P * pg * 3 * sizeof(double));
   L.total = o;
@@ -313,6 +331,14 @@ struct pd_ctx {
   Ctl* h_ctl = nullptr;
   int* h_slots = nullptr;
   Range* h_ranges = nullptr;
+
+  // autotuned choices per slice shape (nx, ny): resident variant and the
+  // two-launch tile sizes (0: default)
+  struct Tuned {
+    int res_variant = 0;
+    int rows = 0, cols = 0;
+  };
+  std::map<std::pair<int, int>, Tuned> tuned;
 
   // captured step graphs of the two-launch path, keyed by launch plan
   struct GraphEntry {
@@ -577,6 +603,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
     int nx, ny, rows, cols, rg, cg;
     bool resident;
     int team;
+    const ResidentVariant* rv;
     int range_off, nranges, npairs;          // resident: one range table
     int row_off, col_off;                    // two-launch path: row and column tables
   };
@@ -590,9 +617,12 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
   bool fits = true;
   for (auto& g : groups) {
     int nx = g.first.nx, ny = g.first.ny;
-    int team = (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only)
-                   ? resident_team(nx) : 0;
-    int maxt = team ? std::min(resident_max_teams(nx), kMaxCounters / 2) : 0;
+    const pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
+    const ResidentVariant* rv =
+        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only)
+            ? resident_variant(nx, tn.res_variant) : nullptr;
+    int team = rv ? rv->team() : 0;
+    int maxt = team ? std::min(rv->max_teams(), kMaxCounters / 2 - 2 * kXcds) : 0;
     if (team && maxt > 0) {
       // split the shape's pairs into co-resident batches
       Launch L{};
@@ -600,6 +630,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
       L.ny = ny;
       L.resident = true;
       L.team = team;
+      L.rv = rv;
       L.range_off = (int)k;
       for (Job* j : g.second) {
         int p = 0;
@@ -625,11 +656,14 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
       L.resident = false;
       L.row_off = (int)k;
       int np = 0;
+      L.rows = rows_valid(tn.rows, nx, ny, c->precision) ? tn.rows : rows_per_wg(nx, ny, c->precision);
+      L.cols = cols_valid(tn.cols, nx, c->precision) ? tn.cols : cols_per_wg(nx, ny, c->precision);
+      L.rg = ny / L.rows;
+      L.cg = nx / L.cols;
       for (Job* j : g.second) {
-        L.rows = j->L.rows;
-        L.cols = j->L.cols;
-        L.rg = j->L.row_groups;
-        L.cg = j->L.col_groups;
+        Vol& V = c->h_vols[j->slot];
+        V.row_groups = L.rg;
+        V.col_groups = L.cg;
         fits &= push_range(j->slot, np * L.rg, 0);
         np += j->L.P;
       }
@@ -685,15 +719,18 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
   // resident launches first (each runs all K iterations of its pairs)
   for (auto& L : launches) {
     if (!L.resident) continue;
-    if ((e = launch_zero(c->d_counters, align_up(2 * sizeof(unsigned) * (size_t)L.npairs), c->stream)) !=
+    // team counters of every team slot of the launch (rounds of 8 teams),
+    // then the per-XCD tickets and the grid arrival counter
+    const size_t slots_ = (size_t)((L.npairs + kXcds - 1) / kXcds) * kXcds;
+    if ((e = launch_zero(c->d_counters, align_up(sizeof(unsigned) * (2 * slots_ + kXcds + 1)), c->stream)) !=
         hipSuccess)
       return e;
     const Range* rr = c->d_ranges + L.range_off;
     double pts = (double)L.npairs * L.nx * L.ny * K;
     const int fenced = (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0;
     e = timed(2, pts, [&] {
-      return launch_resident(L.nx, L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort,
-                             fenced, c->stream);
+      return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
+                          c->stream);
     });
     if (e != hipSuccess) return e;
   }
@@ -1209,6 +1246,200 @@ pd_status pd_kernel_time_reset(pd_ctx* c) {
     c->t_ms[k] = 0.0;
     c->t_points[k] = 0.0;
   }
+  return PD_OK;
+}
+
+pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
+                  int* n_entries) {
+  if (!c || iters < 1 || nz < 1 || max_entries < 0) return PD_ERR_ARG;
+  if (!size_supported(nx) || !size_supported(ny)) return PD_ERR_SIZE;
+  if (n_entries) *n_entries = 0;
+  pd_request r{};
+  r.nx = nx;
+  r.ny = ny;
+  r.nz = nz;
+  r.b0[1] = 1.0;
+  r.voxel[0] = r.voxel[1] = 1.0;
+  r.kernel = PD_KERNEL_DIPOLE;
+  r.lambda = 1e-3;
+  r.tau = r.sigma = 1.4;
+  r.theta = 1.0;
+  r.max_iter = iters;
+  Job j;
+  j.req = r;
+  j.L = layout_of(r, c->precision);
+  j.key = key_of(r);
+  bool fresh = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned != PD_OK) return c->poisoned;
+    size_t off;
+    if (!c->arena.alloc(j.L.total, &off)) return PD_ERR_BUDGET;
+    Table* t = acquire_table(c, j.key, &fresh);
+    if (!t) {
+      c->arena.release(off, j.L.total);
+      return PD_ERR_BUDGET;
+    }
+    if (fresh) t->uploaded = true;   // uploaded below, before any use
+    j.tab = *t;
+    j.off = off;
+    j.slot = c->nslots;              // the reserved descriptor slot
+  }
+  std::vector<pd_tune_entry> all;
+  hipError_t e = hipSuccess;
+  {
+    std::lock_guard<std::mutex> ex(c->exec_mu);
+    (void)hipSetDevice(c->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess && fresh)
+      e = c->precision == PD_FP64 ? upload_table<double>(c, j.key, j.tab) : upload_table<float>(c, j.key, j.tab);
+    // zero state and F delta: every value stays zero, so each configuration
+    // runs the same data-independent arithmetic
+    if (e == hipSuccess) e = launch_zero(c->arena.ptr(j.off), j.L.total, c->stream);
+    if (e == hipSuccess) e = launch_zero(c->d_ctl + j.slot, sizeof(Ctl), c->stream);
+    Range* hr = c->h_ranges + (c->range_cap - 1);
+    *hr = Range{j.slot, 0, 0, 0};
+    const Range* dr = c->d_ranges + (c->range_cap - 1);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
+    Vol& V = c->h_vols[j.slot];
+    auto upload_vol = [&](int rg, int cg) -> hipError_t {
+      fill_vol(c, j, V);
+      V.iters = iters;
+      V.done_base = 0;
+      V.final_it = -1;
+      V.check_last = 0;
+      V.row_groups = rg;
+      V.col_groups = cg;
+      hipError_t r2 = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+      if (r2 == hipSuccess) r2 = hipStreamSynchronize(c->stream);   // V is reused by the next candidate
+      return r2;
+    };
+    auto time_it = [&](auto&& launch, double* best) -> hipError_t {
+      *best = 1e300;
+      for (int rep = 0; rep < 4; ++rep) {
+        hipError_t r2 = hipEventRecord(e0, c->stream);
+        if (r2 == hipSuccess) r2 = launch();
+        if (r2 == hipSuccess) r2 = hipEventRecord(e1, c->stream);
+        if (r2 == hipSuccess) r2 = hipEventSynchronize(e1);
+        if (r2 != hipSuccess) return r2;
+        float ms = 0.f;
+        if ((r2 = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return r2;
+        if (rep > 0) *best = std::min(*best, (double)ms);   // first run warms up
+      }
+      return hipSuccess;
+    };
+    const int P = j.L.P;
+    // resident variants
+    if (e == hipSuccess && c->precision == PD_FP32 && nx == ny) {
+      for (int v = 0; e == hipSuccess && v < resident_variant_count(nx); ++v) {
+        const ResidentVariant* rv = resident_variant(nx, v);
+        int maxt = std::min(rv->max_teams(), kMaxCounters / 2 - 2 * kXcds);
+        if (maxt <= 0) continue;
+        int nteams = std::min(P, maxt);
+        if ((e = upload_vol(rv->team(), rv->team())) != hipSuccess) break;
+        double best = 0;
+        e = time_it([&] {
+          const size_t slots_ = (size_t)((nteams + kXcds - 1) / kXcds) * kXcds;
+          hipError_t r2 = launch_zero(c->d_counters, align_up(sizeof(unsigned) * (2 * slots_ + kXcds + 1)),
+                                      c->stream);
+          if (r2 != hipSuccess) return r2;
+          return rv->launch(nteams, c->d_vols, dr, 1, c->d_ctl, c->d_counters, c->d_abort,
+                            (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0, c->stream);
+        }, &best);
+        if (e == hipSuccess && hipMemcpy(c->h_abort, c->d_abort, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
+            *c->h_abort)
+          e = hipErrorLaunchTimeOut;
+        // time per iteration of all P pairs (nteams pairs per launch)
+        pd_tune_entry t{nx, ny, nz, iters, 0, v, rv->team(), rv->threads(), 0, 0, best * (double)P / nteams};
+        all.push_back(t);
+      }
+    }
+    // two-launch tile sizes
+    for (int rows : {8, row_group_big(nx)}) {
+      if (e != hipSuccess) break;
+      if (!rows_valid(rows, nx, ny, c->precision)) continue;
+      for (int cols : {8, 16}) {
+        if (e != hipSuccess) break;
+        if (!cols_valid(cols, nx, c->precision)) continue;
+        bool dup = false;
+        for (auto& t : all) dup |= t.path == 1 && t.rows == rows && t.cols == cols;
+        if (dup) continue;
+        int rg = ny / rows, cg = nx / cols;
+        if ((e = upload_vol(rg, cg)) != hipSuccess) break;
+        double best = 0;
+        e = time_it([&] {
+          hipError_t r2 = hipSuccess;
+          for (int it = 0; it < iters && r2 == hipSuccess; ++it) {
+            r2 = launch_col(ny, COL_ITER, cols, P * cg, cg, c->d_vols, dr, 1, c->d_ctl, it, c->precision, c->stream);
+            if (r2 == hipSuccess)
+              r2 = launch_row(nx, ROW_ITER, rows, P * rg, rg, c->d_vols, dr, 1, c->d_ctl, it, c->precision,
+                              c->stream);
+          }
+          return r2;
+        }, &best);
+        pd_tune_entry t{nx, ny, nz, iters, 1, -1, 0, 0, rows, cols, best};
+        all.push_back(t);
+      }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = e2;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->arena.release(j.off, j.L.total);
+  release_table(c, j.key);
+  if (e != hipSuccess) {
+    c->poisoned = PD_ERR_HIP;
+    return PD_ERR_HIP;
+  }
+  pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
+  double best_res = 1e300, best_two = 1e300;
+  for (auto& t : all) {
+    if (t.path == 0 && t.ms < best_res) {
+      best_res = t.ms;
+      tn.res_variant = t.variant;
+    }
+    if (t.path == 1 && t.ms < best_two) {
+      best_two = t.ms;
+      tn.rows = t.rows;
+      tn.cols = t.cols;
+    }
+  }
+  c->tuned[{nx, ny}] = tn;
+  int n = 0;
+  for (auto& t : all) {
+    if (entries && n < max_entries) entries[n] = t;
+    ++n;
+  }
+  if (n_entries) *n_entries = std::min(n, max_entries);
+  return PD_OK;
+}
+
+pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
+  if (!c) return PD_ERR_ARG;
+  if (!size_supported(nx) || !size_supported(ny)) return PD_ERR_SIZE;
+  if (variant >= 0 && !(nx == ny && variant < resident_variant_count(nx))) return PD_ERR_ARG;
+  if (rows > 0 && !rows_valid(rows, nx, ny, c->precision)) return PD_ERR_ARG;
+  if (cols > 0 && !cols_valid(cols, nx, c->precision)) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> ex(c->exec_mu);   // between scheduling steps
+  std::lock_guard<std::mutex> lk(c->mu);
+  pd_ctx::Tuned tn;
+  tn.res_variant = variant >= 0 ? variant : 0;
+  tn.rows = rows > 0 ? rows : 0;
+  tn.cols = cols > 0 ? cols : 0;
+  c->tuned[{nx, ny}] = tn;
+  return PD_OK;
+}
+
+pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols) {
+  if (!c) return PD_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
+  if (variant) *variant = (nx == ny && resident_variant_count(nx) > 0) ? tn.res_variant : -1;
+  if (rows) *rows = tn.rows > 0 ? tn.rows : rows_per_wg(nx, ny, c->precision);
+  if (cols) *cols = tn.cols > 0 ? tn.cols : cols_per_wg(nx, ny, c->precision);
   return PD_OK;
 }
 

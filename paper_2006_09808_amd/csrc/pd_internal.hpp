@@ -59,6 +59,23 @@ struct Range {
   int pad;
 };
 
+// Pointers read from a descriptor are generic; telling the compiler they
+// point to global memory lets it use global instead of flat instructions.
+template <typename P>
+__device__ __forceinline__ P* gmem(P* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_assume(!__builtin_amdgcn_is_shared((const void*)p));
+  __builtin_assume(!__builtin_amdgcn_is_private((const void*)p));
+#endif
+  return p;
+}
+
+// Copy a per-length twiddle table into LDS (the butterflies gather from it).
+template <typename C>
+__device__ __forceinline__ void stage_twiddles(C* dst, const C* src, int n, int tid, int nt) {
+  for (int i = tid; i < n; i += nt) dst[i] = src[i];
+}
+
 // Workgroup b -> (slot, pair, group) by binary search over the launch's ranges.
 __device__ __forceinline__ void find_work_b(const Range* __restrict__ ranges, int nranges, int groups, int b,
                                             int& slot, int& pair, int& g) {
@@ -106,11 +123,20 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // resident_team(n) is the workgroups per pair (0: no resident kernel for n);
 // resident_max_teams(n) the teams that can be co-resident on the device.
 // Teams are placed one XCD apart (team t on XCD t mod 8), so a launch covers
-// a multiple of 8 teams; resident_max_teams is such a multiple.
+// a multiple of 8 teams; resident_max_teams is such a multiple.  Each square
+// shape has one or more variants (workgroups per pair x block size);
+// variant 0 is the default, an autotuner may pick another.
 constexpr int kXcds = 8;
-int resident_team(int n);
-int resident_max_teams(int n);
-hipError_t launch_resident(int n, int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
-                           unsigned* counters, int* abort_flag, int fenced, hipStream_t st);
+typedef hipError_t (*resident_launch_fn)(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                                         unsigned* counters, int* abort_flag, int fenced, hipStream_t st);
+struct ResidentVariant {
+  int n;
+  resident_launch_fn launch;
+  int (*max_teams)();
+  int (*team)();
+  int (*threads)();
+};
+int resident_variant_count(int n);                      // 0: no resident kernel for n x n
+const ResidentVariant* resident_variant(int n, int v);  // nullptr if out of range
 
 }  // namespace pdk

@@ -1,5 +1,7 @@
 // Kernels for transform length 192 (row length nx = 192 and/or column length ny = 192),
-// and the resident kernel of 192x192 slices (12 workgroups of 256 threads per pair).
+// and the resident kernel variants of 192x192 slices (workgroups per pair x block size:
+// 12 x 256 threads, 24 x 128 threads).
 #include "pd_resident.hpp"
 PD_INSTANTIATE(192)
-PD_INSTANTIATE_RESIDENT(192, 12, 256)
+PD_INSTANTIATE_RESIDENT(192, 0, 12, 256)
+PD_INSTANTIATE_RESIDENT(192, 1, 24, 128)

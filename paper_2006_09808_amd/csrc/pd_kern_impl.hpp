@@ -70,6 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
   constexpr int QA = F::template QF<-1>();  // forward first radix == inverse last radix
   constexpr int QB = F::template QL<-1>();  // forward last radix == inverse first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
+  __shared__ cpx<T> tw_s[NY];
 
   const int tid = threadIdx.x;
   int slot, pair, g;
@@ -83,9 +84,11 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
   const int nx = V.nx;
   const int c0 = g * S;
   const size_t base = (size_t)pair * (size_t)nx * NY;
-  const cpx<T>* __restrict__ tw = (const cpx<T>*)V.twy;
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twy), NY, tid, kThreads);
+  __syncthreads();
+  const cpx<T>* tw = tw_s;
   const cpx<T>* __restrict__ src =
-      (const cpx<T>*)(MODE == COL_CHECK ? V.ex2 : V.ex) + base + c0;
+      gmem((const cpx<T>*)(MODE == COL_CHECK ? V.ex2 : V.ex)) + base + c0;
 
   cpx<T> a[F::template nq<QA>()][QA];
   cpx<T> b[F::template nq<QB>()][QB];
@@ -98,9 +101,9 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     }
   F::template run<-1>(a, b, lds, tw, tid);
 
-  const T* __restrict__ dtab = (const T*)V.dtab + c0;
+  const T* __restrict__ dtab = gmem((const T*)V.dtab) + c0;
   if constexpr (MODE == COL_SETUP) {
-    cpx<T>* dh = (cpx<T>*)V.dhat + base + c0;
+    cpx<T>* dh = gmem((cpx<T>*)V.dhat) + base + c0;
 #pragma unroll
     for (int q = 0; q < F::template nq<QB>(); ++q)
 #pragma unroll
@@ -110,8 +113,8 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
       }
     return;
   } else if constexpr (MODE == COL_CHECK) {
-    const cpx<T>* __restrict__ dh = (const cpx<T>*)V.dhat + base + c0;
-    const cpx<T>* __restrict__ yh = (const cpx<T>*)V.yhat + base + c0;
+    const cpx<T>* __restrict__ dh = gmem((const cpx<T>*)V.dhat) + base + c0;
+    const cpx<T>* __restrict__ yh = gmem((const cpx<T>*)V.yhat) + base + c0;
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < F::template nq<QB>(); ++q)
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
       }
     block_reduce<3, 0>(acc, tid);
     if (tid == 0) {
-      double* out = V.part_col + ((size_t)pair * groups + g) * 3;
+      double* out = gmem(V.part_col) + ((size_t)pair * groups + g) * 3;
       out[0] = acc[0];
       out[1] = acc[1];
       out[2] = acc[2];
@@ -141,8 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     if constexpr (MODE == COL_ITER) {
       const T sig = (T)V.sigma;
       const T inv1ps = (T)(1.0 / (1.0 + V.sigma));
-      cpx<T>* __restrict__ yh = (cpx<T>*)V.yhat + base + c0;
-      const cpx<T>* __restrict__ dh = (const cpx<T>*)V.dhat + base + c0;
+      cpx<T>* __restrict__ yh = gmem((cpx<T>*)V.yhat) + base + c0;
+      const cpx<T>* __restrict__ dh = gmem((const cpx<T>*)V.dhat) + base + c0;
 #pragma unroll
       for (int q = 0; q < F::template nq<QB>(); ++q)
 #pragma unroll
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     }
     F::sync_before_reuse();
     F::template run<+1>(b, a, lds, tw, tid);
-    cpx<T>* dst = (cpx<T>*)V.ex + base + c0;
+    cpx<T>* dst = gmem((cpx<T>*)V.ex) + base + c0;
 #pragma unroll
     for (int q = 0; q < F::template nq<QA>(); ++q)
 #pragma unroll
@@ -195,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
+  __shared__ cpx<T> tw_s[NX];
 
   const int tid = threadIdx.x;
   int slot, pair, g;
@@ -206,7 +210,9 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   const int ny = V.ny;
   const int r0 = g * S;
   const size_t base = (size_t)pair * (size_t)NX * ny + (size_t)r0 * NX;
-  const cpx<T>* __restrict__ tw = (const cpx<T>*)V.twx;
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), NX, tid, kThreads);
+  __syncthreads();
+  const cpx<T>* tw = tw_s;
   const bool pad_imag = V.half_last && pair == V.P - 1;
   const size_t plane = (size_t)NX * ny;
 
@@ -214,7 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   cpx<T> b[F::template nq<QO>()][QO];
 
   if constexpr (MODE == ROW_FWD_PLANAR) {
-    const T* __restrict__ in = (const T*)V.user_in + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+    const T* __restrict__ in = gmem((const T*)V.user_in) + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
 #pragma unroll
     for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
         }
       }
     F::template run<-1>(b, a, lds, tw, tid);
-    cpx<T>* dst = (cpx<T>*)V.ex + base;
+    cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
     for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       }
     return;
   } else {
-    const cpx<T>* __restrict__ src = (const cpx<T>*)V.ex + base;
+    const cpx<T>* __restrict__ src = gmem((const cpx<T>*)V.ex) + base;
 #pragma unroll
     for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
@@ -247,7 +253,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
     F::template run<+1>(a, b, lds, tw, tid);
 
     if constexpr (MODE == ROW_INV_PLANAR) {
-      T* __restrict__ out = (T*)V.user_out + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+      T* __restrict__ out = gmem((T*)V.user_out) + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
 #pragma unroll
       for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
@@ -266,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       const T theta = (T)V.theta;
       const bool check = V.check_last && it == V.iters - 1;
       const bool last = (it == V.final_it);
-      cpx<T>* __restrict__ chi = (cpx<T>*)V.chi + base;
+      cpx<T>* __restrict__ chi = gmem((cpx<T>*)V.chi) + base;
       cpx<T> c[F::template nq<QO>()][QO];
       double acc[2] = {0.0, 0.0};
 #pragma unroll
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       if (check) {
         block_reduce<2, 2>(acc, tid);
         if (tid == 0) {
-          double* out = V.part_row + ((size_t)pair * groups + g) * 2;
+          double* out = gmem(V.part_row) + ((size_t)pair * groups + g) * 2;
           out[0] = acc[0];
           out[1] = acc[1];
         }
@@ -306,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       if (!last) {
         F::sync_before_reuse();
         F::template run<-1>(b, a, lds, tw, tid);
-        cpx<T>* dst = (cpx<T>*)V.ex + base;
+        cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       if (check) {
         F::sync_before_reuse();
         F::template run<-1>(c, a, lds, tw, tid);
-        cpx<T>* dst = (cpx<T>*)V.ex2 + base;
+        cpx<T>* dst = gmem((cpx<T>*)V.ex2) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll

@@ -22,45 +22,33 @@ PD_DECL(384)
 PD_DECL(512)
 #undef PD_DECL
 
-#define PD_DECL_RES(N)                                                                                     \
-  hipError_t launch_resident_##N(int, const Vol*, const Range*, int, Ctl*, unsigned*, int*, int, hipStream_t); \
-  int resident_team_##N();                                                                                  \
-  int resident_max_teams_##N();
-PD_DECL_RES(64)
-PD_DECL_RES(128)
-PD_DECL_RES(192)
-PD_DECL_RES(256)
+#define PD_DECL_RES(N, V)                                                                                   \
+  hipError_t launch_resident_##N##_##V(int, const Vol*, const Range*, int, Ctl*, unsigned*, int*, int,    \
+                                       hipStream_t);                                                     \
+  int resident_max_teams_##N##_##V();                                                                    \
+  int resident_team_##N##_##V();                                                                         \
+  int resident_threads_##N##_##V();
+#define PD_RES_LIST(X) X(64, 0) X(64, 1) X(128, 0) X(128, 1) X(192, 0) X(192, 1) X(256, 0) X(256, 1) X(256, 2)
+PD_RES_LIST(PD_DECL_RES)
 #undef PD_DECL_RES
 
-int resident_team(int n) {
-  switch (n) {
-    case 64: return resident_team_64();
-    case 128: return resident_team_128();
-    case 192: return resident_team_192();
-    case 256: return resident_team_256();
-    default: return 0;
-  }
+#define PD_RES_ENTRY(N, V) \
+  {N, launch_resident_##N##_##V, resident_max_teams_##N##_##V, resident_team_##N##_##V, resident_threads_##N##_##V},
+static const ResidentVariant kResident[] = {PD_RES_LIST(PD_RES_ENTRY)};
+#undef PD_RES_ENTRY
+#undef PD_RES_LIST
+
+int resident_variant_count(int n) {
+  int k = 0;
+  for (const auto& r : kResident) k += r.n == n;
+  return k;
 }
 
-int resident_max_teams(int n) {
-  switch (n) {
-    case 64: return resident_max_teams_64();
-    case 128: return resident_max_teams_128();
-    case 192: return resident_max_teams_192();
-    case 256: return resident_max_teams_256();
-    default: return 0;
-  }
-}
-
-hipError_t launch_resident(int n, int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
-                           unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {
-  switch (n) {
-    case 64: return launch_resident_64(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
-    case 128: return launch_resident_128(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
-    case 192: return launch_resident_192(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
-    case 256: return launch_resident_256(nteams, vols, ranges, nranges, ctl, counters, abort_flag, fenced, st);
-    default: return hipErrorInvalidValue;
-  }
+const ResidentVariant* resident_variant(int n, int v) {
+  int k = 0;
+  for (const auto& r : kResident)
+    if (r.n == n && k++ == v) return &r;
+  return nullptr;
 }
 
 bool size_supported(int n) {

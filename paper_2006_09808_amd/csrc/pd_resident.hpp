@@ -11,16 +11,15 @@
 // threshold, over-relaxation, forward row FFT) of the PD pseudocode
 // (Sec. II-A), with a team barrier after each phase.
 //
-// Workgroup b of the launch runs on XCD b mod 8 (the dispatcher hands
-// workgroups to the XCDs round robin), and the kernel groups the workgroups of
-// one XCD into teams, so a team's exchange traffic stays in that XCD's L2,
-// the coherence point of all its CUs.  Team barriers then only need each
-// wave's stores to have reached L2 (s_waitcnt) and the exchange loads to skip
-// the CU's L1 (sc1), with no L2 write-back.  Each workgroup checks the XCD it
-// actually runs on (HW_REG_XCC_ID) in a first team barrier; if any member of
-// a team is elsewhere, that team uses agent-scope release/acquire fences
-// (L2 write-back and invalidate) for every barrier instead, which is correct
-// wherever its workgroups run.  The launch is cooperative (every workgroup
+// The kernel groups the workgroups of one XCD into teams (each workgroup
+// reads the XCD it runs on, HW_REG_XCC_ID), so a team's exchange traffic
+// stays in that XCD's L2, the coherence point of all its CUs.  Team barriers
+// then only need each wave's stores to have reached L2 (s_waitcnt) and the
+// exchange loads to skip the CU's L1 (sc1), with no L2 write-back.  If the
+// workgroups are not spread evenly over the XCDs, teams are formed from
+// workgroup indices instead and use agent-scope release/acquire fences (L2
+// write-back and invalidate) for every barrier, which is correct wherever
+// the workgroups run.  The launch is cooperative (every workgroup
 // co-resident); a bounded spin turns a barrier that never completes into an
 // abort flag that every workgroup sees, so the grid always drains.
 #pragma once
@@ -127,7 +126,8 @@ struct Resident {
   static constexpr int NQB = FC::template nq<QB>();
 };
 
-// counters: 2 per team (barrier arrivals, placement check), zeroed per launch.
+// counters: 2 per team slot (barrier arrivals, spare), then kXcds per-XCD
+// tickets and one grid arrival counter; zeroed before every launch.
 template <int NX, int NY, int TEAM, int NT>
 __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
@@ -138,50 +138,75 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
   using T = float;
   __shared__ cpx<T> lds[R::LDS];
   __shared__ cpx<T> dh_s[R::CT * NY];        // F delta of this workgroup's columns, [row][column]
+  __shared__ cpx<T> tw_s[NX + NY];           // twiddles of the row (NX) and column (NY) transforms
   __shared__ int lds_flag;
 
   const int tid = threadIdx.x;
-  // team t = (workgroup's team within its XCD) * 8 + XCD
-  const int b = (int)blockIdx.x;
-  const int xcd = b % kXcds;
-  const int local = b / kXcds;
-  const int t = (local / TEAM) * kXcds + xcd;
+  // Team formation.  Every workgroup reads the XCD it runs on and takes a
+  // ticket among that XCD's workgroups; after one grid-wide arrival all of
+  // them know whether each XCD received exactly its quota of TEAM * rounds
+  // workgroups (the dispatcher deals them out round robin, from whichever
+  // XCD is next).  If so, team t = (ticket / TEAM) * 8 + XCD and every team
+  // lives on one XCD; otherwise the workgroups fall back to
+  // t = (b / 8 / TEAM) * 8 + b % 8 with agent-scope fences at every barrier.
+  const int rounds = (int)gridDim.x / (kXcds * TEAM);
+  unsigned* tickets = counters + 2 * rounds * kXcds;       // kXcds per-XCD tickets, then one grid counter
+  __shared__ int s_team, s_member, s_fenced;
+  if (tid == 0) {
+    const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
+    unsigned ticket = 0xffffffffu;
+    if (here < (unsigned)kXcds) ticket = __hip_atomic_fetch_add(tickets + here, 1u, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    unsigned seen = 0;
+    int fen = 1;
+    if (!arrive_wait(tickets + kXcds, 1u, gridDim.x, 0xffffffffu, &seen, abort_flag)) {
+      fen = -1;
+    } else {
+      bool balanced = true;
+      for (int x = 0; x < kXcds; ++x)
+        balanced &= __hip_atomic_load(tickets + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                    (unsigned)(TEAM * rounds);
+      const int b = (int)blockIdx.x;
+      if (balanced && !force_fenced) {
+        s_team = (int)(ticket / TEAM) * kXcds + (int)here;
+        s_member = (int)(ticket % TEAM);
+        fen = 0;
+      } else {
+        s_team = ((b / kXcds) / TEAM) * kXcds + b % kXcds;
+        s_member = (b / kXcds) % TEAM;
+        fen = 1;
+      }
+    }
+    s_fenced = fen;
+  }
+  __syncthreads();
+  if (s_fenced < 0) return;                   // aborted before any state was touched
+  const int t = s_team;
   if (t >= nteams) return;                    // padding team of the last XCD round
   int slot, pair, m;
-  find_work_b(ranges, nranges, TEAM, t * TEAM + (local % TEAM), slot, pair, m);
+  find_work_b(ranges, nranges, TEAM, t * TEAM + s_member, slot, pair, m);
   const Vol& V = vols[slot];
   if (ctl[slot].stop || V.iters <= 0 || V.check_only) return;   // uniform over the team
   const int iters = V.iters;
   const bool check = V.check_last != 0;
   const bool final_step = V.final_it == iters - 1;
   unsigned* cnt = counters + 2 * t;
-
-  // placement check: one arrival per member, +0x10000 if it is not on XCD t mod 8
-  if (tid == 0) {
-    const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
-    const unsigned add = 1u + ((here == (unsigned)xcd && !force_fenced) ? 0u : 0x10000u);
-    unsigned seen = 0;
-    int fen = 1;
-    if (arrive_wait(counters + 2 * t + 1, add, TEAM, 0xffffu, &seen, abort_flag)) fen = (seen >> 16) != 0;
-    else fen = -1;
-    lds_flag = fen;
-  }
-  __syncthreads();
-  if (lds_flag < 0) return;                   // aborted before any state was touched
-  const bool fenced = lds_flag != 0;
+  const bool fenced = s_fenced != 0;
 
   const size_t plane = (size_t)NX * NY;
   const size_t base = (size_t)pair * plane;
   const int r0 = m * R::RT;
   const int c0 = m * R::CT;
-  const cpx<T>* __restrict__ twx = (const cpx<T>*)V.twx;
-  const cpx<T>* __restrict__ twy = (const cpx<T>*)V.twy;
-  cpx<T>* __restrict__ ex = (cpx<T>*)V.ex + base;
-  cpx<T>* __restrict__ ex2 = (cpx<T>*)V.ex2 + base;
-  cpx<T>* __restrict__ chi_g = (cpx<T>*)V.chi + base;
-  cpx<T>* __restrict__ yh_g = (cpx<T>*)V.yhat + base;
-  const cpx<T>* __restrict__ dh_g = (const cpx<T>*)V.dhat + base;
-  const T* __restrict__ dtab = (const T*)V.dtab;
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), NX, tid, NT);
+  stage_twiddles(tw_s + NX, gmem((const cpx<T>*)V.twy), NY, tid, NT);
+  const cpx<T>* twx = tw_s;
+  const cpx<T>* twy = tw_s + NX;
+  cpx<T>* __restrict__ ex = gmem((cpx<T>*)V.ex) + base;
+  cpx<T>* __restrict__ ex2 = gmem((cpx<T>*)V.ex2) + base;
+  cpx<T>* __restrict__ chi_g = gmem((cpx<T>*)V.chi) + base;
+  cpx<T>* __restrict__ yh_g = gmem((cpx<T>*)V.yhat) + base;
+  const cpx<T>* __restrict__ dh_g = gmem((const cpx<T>*)V.dhat) + base;
+  const T* __restrict__ dtab = gmem((const T*)V.dtab);
   const T tau = (T)V.tau, tl = (T)(V.tau * V.lam), theta = (T)V.theta;
   const T sig = (T)V.sigma, inv1ps = (T)(1.0 / (1.0 + V.sigma));
   const T invN = (T)(1.0 / ((double)NX * (double)NY));
@@ -210,6 +235,8 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
         dk[q][r] = dtab[o];
       }
     }
+
+  __syncthreads();   // twiddle tables staged
 
   // exchange-buffer resources of this pair (the whole [ny][nx] plane)
   const __amdgpu_buffer_rsrc_t rex = buf_rsrc(ex, (unsigned)(plane * sizeof(cpx<T>)));
@@ -315,7 +342,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
       if (do_check) {
         block_reduce<2, 2, NT>(acc_r, tid);
         if (tid == 0) {
-          double* out = V.part_row + ((size_t)pair * TEAM + m) * 2;
+          double* out = gmem(V.part_row) + ((size_t)pair * TEAM + m) * 2;
           out[0] = acc_r[0];
           out[1] = acc_r[1];
         }
@@ -376,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
       }
     block_reduce<3, 0, NT>(acc, tid);
     if (tid == 0) {
-      double* out = V.part_col + ((size_t)pair * TEAM + m) * 3;
+      double* out = gmem(V.part_col) + ((size_t)pair * TEAM + m) * 3;
       out[0] = acc[0];
       out[1] = acc[1];
       out[2] = acc[2];
@@ -428,14 +455,17 @@ int resident_max_teams_t() {
 
 }  // namespace pdk
 
-// Defines the resident launcher of the square N x N slice shape.
-#define PD_INSTANTIATE_RESIDENT(N, TEAM, NT)                                                             \
+// Defines resident variant V of the square N x N slice shape: its launcher,
+// its co-resident team capacity, and its team size and block size.
+#define PD_INSTANTIATE_RESIDENT(N, V, TEAM, NT)                                                          \
   namespace pdk {                                                                                        \
-  hipError_t launch_resident_##N(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl, \
-                                 unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {     \
+  hipError_t launch_resident_##N##_##V(int nteams, const Vol* vols, const Range* ranges, int nranges,    \
+                                       Ctl* ctl, unsigned* counters, int* abort_flag, int fenced,        \
+                                       hipStream_t st) {                                                 \
     return launch_resident_t<N, N, TEAM, NT>(nteams, vols, ranges, nranges, ctl, counters, abort_flag,   \
                                              fenced, st);                                                 \
   }                                                                                                      \
-  int resident_team_##N() { return TEAM; }                                                              \
-  int resident_max_teams_##N() { return resident_max_teams_t<N, N, TEAM, NT>(); }                       \
+  int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT>(); }                 \
+  int resident_team_##N##_##V() { return TEAM; }                                                        \
+  int resident_threads_##N##_##V() { return NT; }                                                       \
   }

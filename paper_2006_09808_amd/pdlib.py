@@ -25,7 +25,8 @@ SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",
            "pd_validate", "pd_kernel_norm", "pd_apply_kernel", "pd_now",
-           "pd_kernel_time", "pd_kernel_time_reset", "pd_graph_stats", "pd_arena_usage")
+           "pd_kernel_time", "pd_kernel_time_reset", "pd_graph_stats", "pd_arena_usage",
+           "pd_tune", "pd_tune_set", "pd_tune_get")
 
 
 class PdConfig(ctypes.Structure):
@@ -43,6 +44,13 @@ class PdRequest(ctypes.Structure):
                 ("theta", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("gap_tol", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("delta", ctypes.c_void_p), ("chi", ctypes.c_void_p)]
+
+
+class PdTuneEntry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("iters", ctypes.c_int),
+                ("path", ctypes.c_int), ("variant", ctypes.c_int), ("team", ctypes.c_int),
+                ("threads", ctypes.c_int), ("rows", ctypes.c_int), ("cols", ctypes.c_int),
+                ("ms", ctypes.c_double)]
 
 
 class PdResult(ctypes.Structure):
@@ -82,9 +90,14 @@ def load_library(path=None):
     lib.pd_kernel_time_reset.argtypes = [c.c_void_p]
     lib.pd_arena_usage.argtypes = [c.c_void_p, c.POINTER(c.c_size_t), c.POINTER(c.c_int), c.POINTER(c.c_int)]
     lib.pd_graph_stats.argtypes = [c.c_void_p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+    lib.pd_tune.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.POINTER(PdTuneEntry), c.c_int,
+                            c.POINTER(c.c_int)]
+    lib.pd_tune_set.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int]
+    lib.pd_tune_get.argtypes = [c.c_void_p, c.c_int, c.c_int, c.POINTER(c.c_int), c.POINTER(c.c_int),
+                                c.POINTER(c.c_int)]
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
                  "pd_kernel_norm", "pd_apply_kernel", "pd_kernel_time", "pd_kernel_time_reset",
-                 "pd_graph_stats", "pd_arena_usage"):
+                 "pd_graph_stats", "pd_arena_usage", "pd_tune", "pd_tune_set", "pd_tune_get"):
         getattr(lib, name).restype = c.c_int32
     if path is None:
         _lib = lib
@@ -268,6 +281,47 @@ class Solver:
 
     def kernel_time_reset(self):
         self.lib.pd_kernel_time_reset(self._ctx)
+
+    def tune(self, nx, ny, nz, iters=20):
+        """Time every kernel configuration of the nx x ny shape and make the
+        fastest the context's choice.  Returns the list of timings."""
+        buf = (PdTuneEntry * 32)()
+        n = ctypes.c_int(0)
+        st = self.lib.pd_tune(self._ctx, int(nx), int(ny), int(nz), int(iters), buf, 32, ctypes.byref(n))
+        if st != PD_OK:
+            raise PdError(st, "pd_tune")
+        out = []
+        for e in buf[:n.value]:
+            out.append({"path": "resident" if e.path == 0 else "two_launch", "variant": e.variant,
+                        "team": e.team, "threads": e.threads, "rows": e.rows, "cols": e.cols,
+                        "ms": e.ms, "nz": e.nz, "iters": e.iters})
+        return out
+
+    def tune_get(self, nx, ny):
+        v, r, cl = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+        st = self.lib.pd_tune_get(self._ctx, int(nx), int(ny), ctypes.byref(v), ctypes.byref(r), ctypes.byref(cl))
+        if st != PD_OK:
+            raise PdError(st, "pd_tune_get")
+        return {"variant": v.value, "rows": r.value, "cols": cl.value}
+
+    def tune_set(self, nx, ny, variant=-1, rows=0, cols=0):
+        st = self.lib.pd_tune_set(self._ctx, int(nx), int(ny), int(variant), int(rows), int(cols))
+        if st != PD_OK:
+            raise PdError(st, "pd_tune_set")
+
+    def save_tuning(self, path, shapes):
+        """Write the choices of the given (nx, ny) shapes as JSON."""
+        import json
+        with open(path, "w") as f:
+            json.dump({"%dx%d" % (nx, ny): self.tune_get(nx, ny) for nx, ny in shapes}, f, indent=1)
+
+    def load_tuning(self, path):
+        import json
+        with open(path) as f:
+            d = json.load(f)
+        for k, v in d.items():
+            nx, ny = (int(t) for t in k.split("x"))
+            self.tune_set(nx, ny, v["variant"], v["rows"], v["cols"])
 
     def graph_stats(self):
         """(steps captured into HIP graphs, steps replayed from one)."""

@@ -349,3 +349,48 @@ def test_graph_replay_equals_eager(torch_mod, gap_tol):
         captures, replays = g.graph_stats()
         _say("graph captures %d replays %d" % (captures, replays))
         assert captures >= 1 and replays >= 8
+
+
+@pytest.mark.parametrize("n,nz", [(256, 6), (128, 5), (64, 3), (192, 4), (96, 3)])
+def test_autotune_configurations_agree(torch_mod, n, nz):
+    """Every configuration the autotuner can pick distributes the same
+    arithmetic differently, so chi is bitwise identical across them."""
+    import paper_2006_09808_amd as pd
+    w, delta = make_case(91, nz, n, n if n != 96 else 64, lam=1e-3, max_iter=33)
+    ny, nx = delta.shape[1], delta.shape[2]
+    sp = w.solver_params()
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        table = s.tune(nx, ny, nz, iters=10)
+        _say("tune %dx%d: %s" % (nx, ny, ["%s v%d %dx%d r%d c%d %.3f ms" % (t["path"], t["variant"], t["team"],
+                                                                          t["threads"], t["rows"], t["cols"], t["ms"])
+                                          for t in table]))
+        assert len(table) >= 1
+        choice = s.tune_get(nx, ny)
+        res = [t for t in table if t["path"] == "resident"]
+        two = [t for t in table if t["path"] == "two_launch"]
+        if res:
+            assert choice["variant"] == min(res, key=lambda t: t["ms"])["variant"]
+        best_two = min(two, key=lambda t: t["ms"])
+        assert (choice["rows"], choice["cols"]) == (best_two["rows"], best_two["cols"])
+        ref, iref = gpu_solve(s, torch_mod, delta, **sp)
+        for t in table:
+            if t["path"] == "resident":
+                s.tune_set(nx, ny, t["variant"], 0, 0)
+            else:
+                s2 = pd.Solver(arena_bytes=1 << 30, device=0, resident=False)
+                s2.tune_set(nx, ny, -1, t["rows"], t["cols"])
+                got, _ = gpu_solve(s2, torch_mod, delta, **sp)
+                s2.close()
+                if res:       # two-launch vs resident: same values up to rounding
+                    assert rel_l2(got, ref) <= 1e-5
+                else:
+                    np.testing.assert_array_equal(got, ref)
+                continue
+            got, info = gpu_solve(s, torch_mod, delta, **sp)
+            np.testing.assert_array_equal(got, ref)
+        oref, _ = oracle.solve(delta.astype(np.float64), **sp)
+        assert rel_l2(ref, oref) <= REL_TOL
+        with pytest.raises(pd.PdError):
+            s.tune_set(nx, ny, 99, 0, 0)
+        with pytest.raises(pd.PdError):
+            s.tune_set(nx, ny, -1, 7, 0)
