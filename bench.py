@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-slice", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the single-slice, uneven-batch and 256-slice lines")
     ap.add_argument("--cpu-sample-slices", type=int, default=16)
     ap.add_argument("--cpu-sample-iters", type=int, default=60)
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -152,6 +154,74 @@ def serving(rate, seconds, arena_gb):
                     "sizes": list(pd_inputs.SERVING_SIZES), "slices": [16, 64],
                     "gap_tol": 1e-5, "max_iter": 1000})
     return summary
+
+
+def _device_delta(s, w, dev):
+    import torch
+    import pd_inputs
+    field = s.apply_kernel(torch.from_numpy(w.chi_true.astype(np.float32)).to(dev))
+    d = pd_inputs.make_delta(field.cpu().numpy().astype(np.float64), w.eta, w.rho)
+    return torch.from_numpy(d.astype(np.float32)).to(dev)
+
+
+def other_workloads(reps=20):
+    """The single-slice latency case, the uneven batch and a stack of 256
+    slices (its state, 96 MiB, no longer fits the 256 MiB last-level cache
+    together with the exchange buffers), each on a fresh context."""
+    import torch
+    import pd_inputs
+    import paper_2006_09808_amd as pd
+    dev = torch.device("cuda", 0)
+    out = {}
+    w = pd_inputs.config1()
+    with pd.Solver(arena_bytes=256 << 20, device=0) as s:
+        d = _device_delta(s, w, dev)
+        chi = torch.empty_like(d)
+        sp = w.solver_params()
+        lat = []
+        for i in range(reps + 3):
+            t0 = pd.now()
+            (t,) = s.submit([(d, chi, sp)])
+            r = s.poll(t, -1)
+            if r["status"] != pd.PD_OK:
+                raise RuntimeError("single-slice solve failed: %r" % (r,))
+            if i >= 3:
+                lat.append(pd.now() - t0)
+        lat.sort()
+        out["single_64x64x1_200it"] = {"median_ms": lat[len(lat) // 2] * 1e3, "min_ms": lat[0] * 1e3,
+                                       "solves": len(lat)}
+    vols = pd_inputs.config3()
+    with pd.Solver(arena_bytes=8 << 30, device=0) as s:
+        jobs = []
+        for w in vols:
+            d = _device_delta(s, w, dev)
+            jobs.append((d, torch.empty_like(d), w.solver_params()))
+        walls = []
+        for _ in range(3):
+            t0 = pd.now()
+            infos = [s.poll(t, -1) for t in s.submit(jobs)]
+            walls.append(pd.now() - t0)
+        vit = sum(int(j[0].numel()) * i["iterations"] for j, i in zip(jobs, infos))
+        out["uneven_128x32_256x48_384x24_1e-5"] = {
+            "wall_ms": min(walls) * 1e3, "iterations": [i["iterations"] for i in infos],
+            "rel_gap": [i["rel_gap"] for i in infos], "voxel_iterations_per_s": vit / min(walls)}
+    w = pd_inputs.random_stack(2500, 256, NY, NX, lam=1e-3, max_iter=ITERS)
+    with pd.Solver(arena_bytes=4 << 30, device=0) as s:
+        d = _device_delta(s, w, dev)
+        chi = torch.empty_like(d)
+        sp = w.solver_params()
+        best = None
+        for _ in range(3):
+            t0 = pd.now()
+            (t,) = s.submit([(d, chi, sp)])
+            r = s.poll(t, -1)
+            if r["status"] != pd.PD_OK:
+                raise RuntimeError("256-slice solve failed")
+            dt = pd.now() - t0
+            best = dt if best is None else min(best, dt)
+        out["batched_256x256x256_500it"] = {"ms": best * 1e3,
+                                            "voxel_iterations_per_s": 256 * NX * NY * ITERS / best}
+    return out
 
 
 def cpu_baseline(w, nslices, iters):
@@ -294,6 +364,8 @@ def main():
         "rel_gap": info["rel_gap"],
         "autotune": {"choice": tune_choice, "timings": tune_table},
     }
+    if not a.no_workloads:
+        out["workloads"] = other_workloads()
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
     if not a.no_cpu_baseline:

@@ -81,7 +81,8 @@ typedef struct {
   int precision;       /* PD_FP32 (default) or PD_FP64                            */
   int step_iters;      /* most iterations launched between host scheduling points
                           (requests are admitted and retired only there); a step
-                          also ends at every request's next gap check; 0 = 100   */
+                          also ends at every request's next gap check; 0 = 500,
+                          or 50 while requests wait in the queue                 */
   int flags;           /* PD_FLAG_* */
 } pd_config;
 

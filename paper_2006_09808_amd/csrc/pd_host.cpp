@@ -37,7 +37,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultSlots = 256;
-constexpr int kDefaultStep = 100;
+constexpr int kDefaultStep = 500;       // step cap while no request waits for admission
+constexpr int kQueuedStep = 50;         // step cap while requests wait in the queue
 constexpr int kMaxStep = 1 << 20;
 constexpr int kMaxGraphs = 32;
 constexpr int kMaxCounters = 4096;   // team barrier counters per resident launch (2 per team)
@@ -556,8 +557,8 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
 // One scheduling step over all resident jobs: K iterations for every job,
 // where K ends the step at every job's next gap check (or its last
 // iteration), so checks and stop decisions only happen at step ends.
-hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act) {
-  int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : kDefaultStep;
+hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued) {
+  int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : (queued ? kQueuedStep : kDefaultStep);
   bool any_check_only = false;
   for (auto& j : act) {
     if (j->req.max_iter == 0) {
@@ -908,13 +909,14 @@ void worker_main(pd_ctx* c) {
     if (!ok) continue;   // poisoned: next loop turn fails everything
     if (c->active.empty()) continue;
     std::vector<std::shared_ptr<Job>> act = c->active;
+    const bool queued = !c->queue.empty();
     lk.unlock();
 
     hipError_t e;
     std::vector<std::shared_ptr<Job>> retired;
     {
       std::lock_guard<std::mutex> ex(c->exec_mu);
-      e = run_step(c, act);
+      e = run_step(c, act, queued);
       if (e == hipSuccess) {
         for (auto& j : act) {
           const Ctl& C = c->h_ctl[j->slot];
