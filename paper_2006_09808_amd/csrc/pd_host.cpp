@@ -41,7 +41,6 @@ constexpr int kDefaultStep = 500;       // step cap while no request waits for a
 constexpr int kQueuedStep = 50;         // step cap while requests wait in the queue
 constexpr int kMaxStep = 1 << 20;
 constexpr int kMaxGraphs = 32;
-constexpr int kMaxCounters = 4096;   // team barrier counters per resident launch (2 per team)
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline bool isfin(double x) { return std::isfinite(x); }
@@ -325,7 +324,7 @@ struct pd_ctx {
   int* d_slots = nullptr;      // nslots
   Range* d_ranges = nullptr;   // range_cap
   size_t range_cap = 0;        // entries of d_ranges / h_ranges; the last is pd_apply_kernel's
-  unsigned* d_counters = nullptr;   // kMaxCounters team-barrier counters
+  unsigned* d_counters = nullptr;   // resident-launch counters, counter_bytes(kMaxTeamSlots)
   int* d_abort = nullptr;           // set by a resident launch whose barrier timed out
   int* h_abort = nullptr;
   Vol* h_vols = nullptr;
@@ -623,7 +622,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
         (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only)
             ? resident_variant(nx, tn.res_variant) : nullptr;
     int team = rv ? rv->team() : 0;
-    int maxt = team ? std::min(rv->max_teams(), kMaxCounters / 2 - 2 * kXcds) : 0;
+    int maxt = team ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
     if (team && maxt > 0) {
       // split the shape's pairs into co-resident batches
       Launch L{};
@@ -723,7 +722,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     // team counters of every team slot of the launch (rounds of 8 teams),
     // then the per-XCD tickets and the grid arrival counter
     const size_t slots_ = (size_t)((L.npairs + kXcds - 1) / kXcds) * kXcds;
-    if ((e = launch_zero(c->d_counters, align_up(sizeof(unsigned) * (2 * slots_ + kXcds + 1)), c->stream)) !=
+    if ((e = launch_zero(c->d_counters, align_up(counter_bytes(slots_)), c->stream)) !=
         hipSuccess)
       return e;
     const Range* rr = c->d_ranges + L.range_off;
@@ -1025,7 +1024,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->range_cap = 4 * (size_t)c->nslots + 4096;
   c->ctl_bytes = align_up(sizeof(Vol) * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
                  align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * c->range_cap) +
-                 align_up(sizeof(unsigned) * kMaxCounters) + align_up(sizeof(int));
+                 align_up(counter_bytes(kMaxTeamSlots)) + align_up(sizeof(int));
   if (!c->arena.alloc(c->ctl_bytes, &c->ctl_off)) return PD_ERR_BUDGET;
   char* p = c->arena.ptr(c->ctl_off);
   c->d_vols = (Vol*)p;
@@ -1037,7 +1036,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->d_ranges = (Range*)p;
   p += align_up(sizeof(Range) * c->range_cap);
   c->d_counters = (unsigned*)p;
-  p += align_up(sizeof(unsigned) * kMaxCounters);
+  p += align_up(counter_bytes(kMaxTeamSlots));
   c->d_abort = (int*)p;
 
   if (cfg->stream) {
@@ -1336,14 +1335,14 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
     if (e == hipSuccess && c->precision == PD_FP32 && nx == ny) {
       for (int v = 0; e == hipSuccess && v < resident_variant_count(nx); ++v) {
         const ResidentVariant* rv = resident_variant(nx, v);
-        int maxt = std::min(rv->max_teams(), kMaxCounters / 2 - 2 * kXcds);
+        int maxt = std::min(rv->max_teams(), kMaxTeamSlots);
         if (maxt <= 0) continue;
         int nteams = std::min(P, maxt);
         if ((e = upload_vol(rv->team(), rv->team())) != hipSuccess) break;
         double best = 0;
         e = time_it([&] {
           const size_t slots_ = (size_t)((nteams + kXcds - 1) / kXcds) * kXcds;
-          hipError_t r2 = launch_zero(c->d_counters, align_up(sizeof(unsigned) * (2 * slots_ + kXcds + 1)),
+          hipError_t r2 = launch_zero(c->d_counters, align_up(counter_bytes(slots_)),
                                       c->stream);
           if (r2 != hipSuccess) return r2;
           return rv->launch(nteams, c->d_vols, dr, 1, c->d_ctl, c->d_counters, c->d_abort,

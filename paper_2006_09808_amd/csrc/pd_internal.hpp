@@ -127,6 +127,15 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // shape has one or more variants (workgroups per pair x block size);
 // variant 0 is the default, an autotuner may pick another.
 constexpr int kXcds = 8;
+// Resident-launch synchronisation counters, one per 256-byte line so that
+// teams spinning on their own barrier never share a line: team slot t at
+// word t * kCounterStride, then kXcds per-XCD tickets, then the grid arrival
+// counter.  kMaxTeamSlots bounds the teams of one launch.
+constexpr int kCounterStride = 64;
+constexpr int kMaxTeamSlots = 2048;
+inline size_t counter_bytes(size_t team_slots) {
+  return (team_slots + kXcds + 1) * kCounterStride * sizeof(unsigned);
+}
 typedef hipError_t (*resident_launch_fn)(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                                          unsigned* counters, int* abort_flag, int fenced, hipStream_t st);
 struct ResidentVariant {

@@ -126,8 +126,9 @@ struct Resident {
   static constexpr int NQB = FC::template nq<QB>();
 };
 
-// counters: 2 per team slot (barrier arrivals, spare), then kXcds per-XCD
-// tickets and one grid arrival counter; zeroed before every launch.
+// counters: one barrier counter per team slot, then kXcds per-XCD tickets and
+// the grid arrival counter, kCounterStride words apart; zeroed before every
+// launch.
 template <int NX, int NY, int TEAM, int NT>
 __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
@@ -150,21 +151,21 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
   // lives on one XCD; otherwise the workgroups fall back to
   // t = (b / 8 / TEAM) * 8 + b % 8 with agent-scope fences at every barrier.
   const int rounds = (int)gridDim.x / (kXcds * TEAM);
-  unsigned* tickets = counters + 2 * rounds * kXcds;       // kXcds per-XCD tickets, then one grid counter
+  unsigned* tickets = counters + (size_t)rounds * kXcds * kCounterStride;   // per-XCD tickets, grid counter
   __shared__ int s_team, s_member, s_fenced;
   if (tid == 0) {
     const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
     unsigned ticket = 0xffffffffu;
-    if (here < (unsigned)kXcds) ticket = __hip_atomic_fetch_add(tickets + here, 1u, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    if (here < (unsigned)kXcds) ticket = __hip_atomic_fetch_add(tickets + here * kCounterStride, 1u,
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned seen = 0;
     int fen = 1;
-    if (!arrive_wait(tickets + kXcds, 1u, gridDim.x, 0xffffffffu, &seen, abort_flag)) {
+    if (!arrive_wait(tickets + kXcds * kCounterStride, 1u, gridDim.x, 0xffffffffu, &seen, abort_flag)) {
       fen = -1;
     } else {
       bool balanced = true;
       for (int x = 0; x < kXcds; ++x)
-        balanced &= __hip_atomic_load(tickets + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+        balanced &= __hip_atomic_load(tickets + x * kCounterStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                     (unsigned)(TEAM * rounds);
       const int b = (int)blockIdx.x;
       if (balanced && !force_fenced) {
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
   const int iters = V.iters;
   const bool check = V.check_last != 0;
   const bool final_step = V.final_it == iters - 1;
-  unsigned* cnt = counters + 2 * t;
+  unsigned* cnt = counters + (size_t)t * kCounterStride;
   const bool fenced = s_fenced != 0;
 
   const size_t plane = (size_t)NX * NY;
