@@ -1,0 +1,176 @@
+"""FP64 CPU oracle for the weighted total-variation model of Eq. (1) of
+Wang, Cai et al., "Positive Contrast Susceptibility MR Imaging Using GPU-based
+Primal-Dual Algorithm" (arXiv:2006.09808).
+
+TEST INFRASTRUCTURE ONLY.  Like pd_oracle, this is the plain reference the HIP
+solver's TV model is checked against; only the test-suite, the smoke check and
+the benchmark's CPU-baseline leg may import it.  It shares no code with the HIP
+library and takes no input or expected value from it.
+
+What it computes (Sec. II-A, Eq. (1) and the PD pseudocode), per 2-D slice:
+
+    minimise over chi   lam/2 || W (D chi - delta) ||_2^2  +  || M G chi ||_1
+
+with K = [W D ; M G], the data term F1(z) = lam/2 ||z - W delta||^2, the
+regulariser F2(v) = sum over voxels of |v(r)|_2 (isotropic) and no own term
+for chi.  The iteration follows the pseudocode's order:
+
+    p      <- (p + sigma (W D chibar - W delta)) / (1 + sigma / lam)   prox of F1*
+    q      <- v / max(1, |v|),  v = q + sigma M G chibar (per voxel)   prox of F2*
+    chi'   <- chi - tau D* W* p - tau G* M* q                          primal step
+    chibar <- chi' + theta (chi' - chi)                                over-relaxation
+
+Readings of the paper used here (it is silent or ambiguous on these points):
+  * lam weights the data term, as Eq. (1) prints it and as the pseudocode's
+    dual prox (division by 1 + sigma/lam) implies.  (The L1-prior path of
+    pd_oracle puts lam on the L1 term instead; that path is a different model.)
+  * The dual prox subtracts W delta: Eq. (1) weights the whole residual
+    D chi - delta.  The pseudocode's line writes the field map unweighted; the
+    two agree for W = I.
+  * G is the in-plane (2-D) forward difference, divided by the voxel size
+    (dx, dy), with the last difference along each axis set to zero (Neumann
+    boundary); slices stay independent (Sec. II-C, strategy (2)).  G* is its
+    exact adjoint.  The paper's "all three dimensions" is the 3-D variant,
+    which couples slices and is not this model.
+  * The L1 norm of the gradient field is the isotropic one (the Euclidean
+    norm of (g_x, g_y) per voxel, summed): the pseudocode's q update divides
+    the 2-vector by max(1, its norm), the projection onto that norm's dual
+    ball.  M multiplies both components.
+  * W and M are real, per-voxel (diagonal) operators; D is the dipole kernel
+    of pd_oracle (real and even, so D* = D).
+  * Step sizes: tau sigma L^2 < 1 strictly, with the bound
+    L^2 <= max|W|^2 max|D|^2 + max|M|^2 (4/dx^2 + 4/dy^2) on ||K||^2.
+  * Exactly max_iter updates; the result is chi after the last update.  The
+    paper's stop rule is the iteration count; no gap is defined here.
+"""
+
+import numpy as np
+
+from .pd_oracle import apply_A, dipole_kernel, kernel_norm
+
+__all__ = ["grad", "grad_adj", "grad_norm_bound", "check_steps_tv", "objective_tv",
+           "prox_data_dual", "proj_unit_ball", "solve_tv"]
+
+
+# ---------------------------------------------------------------------------
+# In-plane gradient G and its adjoint G*
+# ---------------------------------------------------------------------------
+
+def grad(x, voxel=(1.0, 1.0)):
+    """(g_x, g_y) of x[..., ny, nx]: forward differences divided by the voxel
+    size; the last column of g_x and the last row of g_y are zero."""
+    x = np.asarray(x, dtype=np.float64)
+    dx, dy = float(voxel[0]), float(voxel[1])
+    gx = np.zeros_like(x)
+    gy = np.zeros_like(x)
+    gx[..., :, :-1] = (x[..., :, 1:] - x[..., :, :-1]) / dx
+    gy[..., :-1, :] = (x[..., 1:, :] - x[..., :-1, :]) / dy
+    return gx, gy
+
+
+def grad_adj(qx, qy, voxel=(1.0, 1.0)):
+    """G* (qx, qy), the adjoint of grad: for each axis, element i receives
+    +q[i-1] (if i-1 is a difference the gradient computes) and -q[i] (if i is
+    one), divided by the voxel size along that axis."""
+    qx = np.asarray(qx, dtype=np.float64)
+    qy = np.asarray(qy, dtype=np.float64)
+    dx, dy = float(voxel[0]), float(voxel[1])
+    out = np.zeros(np.broadcast(qx, qy).shape)
+    # x: differences i = 0 .. nx-2 touch elements i (weight -1) and i+1 (+1)
+    out[..., :, :-1] -= qx[..., :, :-1] / dx
+    out[..., :, 1:] += qx[..., :, :-1] / dx
+    out[..., :-1, :] -= qy[..., :-1, :] / dy
+    out[..., 1:, :] += qy[..., :-1, :] / dy
+    return out
+
+
+def grad_norm_bound(voxel=(1.0, 1.0)):
+    """Upper bound 4/dx^2 + 4/dy^2 on ||G||^2 (each axis' difference operator
+    has norm at most 2/d)."""
+    dx, dy = float(voxel[0]), float(voxel[1])
+    return 4.0 / (dx * dx) + 4.0 / (dy * dy)
+
+
+def check_steps_tv(tau, sigma, theta, D, W, M, voxel=(1.0, 1.0)):
+    """Chambolle-Pock condition tau sigma ||K||^2 < 1 with the bound above."""
+    if not (tau > 0 and sigma > 0):
+        raise ValueError("tau and sigma must be positive")
+    if not (0.0 <= theta <= 1.0):
+        raise ValueError("theta must lie in [0, 1]")
+    wmax = float(np.max(np.abs(W))) if np.size(W) else 0.0
+    mmax = float(np.max(np.abs(M))) if np.size(M) else 0.0
+    L2 = wmax * wmax * kernel_norm(D) ** 2 + mmax * mmax * grad_norm_bound(voxel)
+    if not (tau * sigma * L2 < 1.0):
+        raise ValueError("step sizes violate tau*sigma*||K||^2 < 1")
+
+
+def objective_tv(chi, delta, W, M, D, lam, voxel=(1.0, 1.0)):
+    """lam/2 ||W (A chi - delta)||^2 + sum |M G chi|_2 over the whole stack."""
+    r = np.asarray(W) * (apply_A(chi, D) - np.asarray(delta, dtype=np.float64))
+    gx, gy = grad(chi, voxel)
+    M = np.asarray(M, dtype=np.float64)
+    return 0.5 * lam * float(np.sum(r * r)) + float(np.sum(np.sqrt((M * gx) ** 2 + (M * gy) ** 2)))
+
+
+# ---------------------------------------------------------------------------
+# Proximal maps of the two dual terms
+# ---------------------------------------------------------------------------
+
+def prox_data_dual(w, b, sigma, lam):
+    """prox of sigma F1*, F1*(p) = 1/(2 lam)||p||^2 + <p, b> (b = W delta):
+    argmin_p sigma F1*(p) + 1/2||p - w||^2 = (w - sigma b) / (1 + sigma / lam)."""
+    return (np.asarray(w, dtype=np.float64) - sigma * np.asarray(b, dtype=np.float64)) / (1.0 + sigma / lam)
+
+
+def proj_unit_ball(vx, vy):
+    """Per-voxel projection of the 2-vector (vx, vy) onto the Euclidean unit
+    ball: v / max(1, |v|) (prox of sigma F2* for any sigma)."""
+    s = np.maximum(1.0, np.sqrt(vx * vx + vy * vy))
+    return vx / s, vy / s
+
+
+# ---------------------------------------------------------------------------
+# The primal-dual solve
+# ---------------------------------------------------------------------------
+
+def solve_tv(delta, weight, mask, lam, tau, sigma, theta=1.0, max_iter=200,
+             b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kind="dipole", history=None):
+    """PD iteration of the paper's pseudocode for Eq. (1) on a stack
+    delta[nz, ny, nx] with weights W and mask M of the same shape.
+
+    Returns (chi, info) with info = {iterations, objective}.  If `history` is a
+    list, the objective after every update is appended to it.
+    """
+    delta = np.asarray(delta, dtype=np.float64)
+    if delta.ndim == 2:
+        delta = delta[None]
+    if delta.ndim != 3:
+        raise ValueError("delta must be [nz, ny, nx]")
+    W = np.broadcast_to(np.asarray(weight, dtype=np.float64), delta.shape)
+    M = np.broadcast_to(np.asarray(mask, dtype=np.float64), delta.shape)
+    if not lam > 0:
+        raise ValueError("lam must be positive")
+    if max_iter < 0:
+        raise ValueError("max_iter must be >= 0")
+    nz, ny, nx = delta.shape
+    D = dipole_kernel(nx, ny, b0, voxel, kind)
+    check_steps_tv(tau, sigma, theta, D, W, M, voxel)
+
+    b = W * delta
+    # initial values: chi_0 = p_0 = q_0 = 0, chibar_0 = chi_0
+    chi = np.zeros_like(delta)
+    p = np.zeros_like(delta)
+    qx = np.zeros_like(delta)
+    qy = np.zeros_like(delta)
+    chibar = chi.copy()
+    for _ in range(max_iter):
+        p = prox_data_dual(p + sigma * W * apply_A(chibar, D), b, sigma, lam)
+        gx, gy = grad(chibar, voxel)
+        qx, qy = proj_unit_ball(qx + sigma * M * gx, qy + sigma * M * gy)
+        chi_new = chi - tau * apply_A(W * p, D) - tau * grad_adj(M * qx, M * qy, voxel)
+        chibar = chi_new + theta * (chi_new - chi)
+        chi = chi_new
+        if history is not None:
+            history.append(objective_tv(chi, delta, W, M, D, lam, voxel))
+    return chi, {"iterations": int(max_iter),
+                 "objective": objective_tv(chi, delta, W, M, D, lam, voxel)}
