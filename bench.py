@@ -224,6 +224,54 @@ def other_workloads(reps=20):
     return out
 
 
+# weighted TV model: algorithmic HBM bytes per slice-pair point of each launch
+# (FP32, complex pair layout, 8 B per field): column kernel reads and writes
+# the exchange field (16); dual row kernel reads ex, p, W, delta, chibar, q_x,
+# q_y, M and writes p, q_x, q_y, ex (96); primal row kernel reads ex, chi, q_x,
+# q_y, M and writes chi, chibar, ex (64).  Per voxel-iteration:
+# (2 x 16 + 96 + 64) / 2 = 96 B.
+TV_BYTES_PER_VOXEL_IT = 96.0
+TV_COL_BYTES_PER_POINT = 16.0
+TV_ROW_BYTES_PER_POINT = 80.0       # mean of the dual (96) and primal (64) row kernels
+
+
+def tv_workload(nz=64, n=256, iters=500, reps=3):
+    """The weighted TV model of Eq. (1) on nz slices of n x n: wall time per
+    solve and the kernels' HIP-event time and algorithmic bandwidth."""
+    import torch
+    import pd_inputs
+    import paper_2006_09808_amd as pd
+    dev = torch.device("cuda", 0)
+    w = pd_inputs.tv_stack(6000, nz, n, n, max_iter=iters)
+    with pd.Solver(arena_bytes=4 << 30, device=0, time_kernels=True) as s:
+        d = _device_delta(s, w, dev)
+        W = torch.from_numpy(w.weight.astype(np.float32)).to(dev)
+        M = torch.from_numpy(w.mask.astype(np.float32)).to(dev)
+        chi = torch.empty_like(d)
+        sp = dict(w.solver_params(), model="tv", weight=W, mask=M)
+        s.poll(s.submit([(d, chi, sp)])[0], -1)        # warm-up
+        s.kernel_time_reset()
+        best = None
+        for _ in range(reps):
+            t0 = pd.now()
+            r = s.poll(s.submit([(d, chi, sp)])[0], -1)
+            if r["status"] != pd.PD_OK or r["iterations"] != iters:
+                raise RuntimeError("TV solve failed: %r" % (r,))
+            dt = pd.now() - t0
+            best = dt if best is None else min(best, dt)
+        kt = {name: s.kernel_time(kind) for name, kind in (("tv_column", pd.KIND_TV_COLUMN), ("tv_row", pd.KIND_TV_ROW))}
+    vit = nz * n * n * iters
+    out = {"workload": "weighted TV (Eq. (1)), %d slices of %dx%d, %d iterations" % (nz, n, n, iters),
+           "ms": best * 1e3, "voxel_iterations_per_s": vit / best,
+           "bytes_per_voxel_iteration": TV_BYTES_PER_VOXEL_IT,
+           "achieved_GBs_wall": TV_BYTES_PER_VOXEL_IT * vit / best / 1e9, "kernels": {}}
+    for name, (nl, ms, pts) in kt.items():
+        if nl:
+            bpp = TV_COL_BYTES_PER_POINT if name == "tv_column" else TV_ROW_BYTES_PER_POINT
+            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9}
+    return out
+
+
 def cpu_baseline(w, nslices, iters):
     """FP64 oracle on a bounded sample of the same workload (first `nslices`
     slices, `iters` iterations), on this host's cores."""
@@ -366,6 +414,7 @@ def main():
     }
     if not a.no_workloads:
         out["workloads"] = other_workloads()
+        out["workloads"]["tv_256x256x64_500it"] = tv_workload()
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
     if not a.no_cpu_baseline:

@@ -42,7 +42,8 @@ enum {
   PD_PENDING = 1,          /* ticket not finished (pd_poll timeout)               */
   PD_ERR_ARG = -1,         /* null pointer, bad enum, non-finite parameter, ...   */
   PD_ERR_SIZE = -2,        /* nx or ny not in the supported set, nz < 1          */
-  PD_ERR_STEP = -3,        /* tau*sigma*max|D|^2 >= 1, theta outside [0, 1], ... */
+  PD_ERR_STEP = -3,        /* tau*sigma*max|D|^2 >= 1, theta outside [0, 1], ...
+                              (TV model: tau*sigma*L2 >= 1, found at admission)   */
   PD_ERR_BUDGET = -4,      /* request can never fit in the context's arena       */
   PD_ERR_NONFINITE = -5,   /* a non-finite value appeared in the duality gap     */
   PD_ERR_HIP = -6,         /* HIP runtime error; the context is unusable         */
@@ -53,6 +54,22 @@ enum {
 
 enum { PD_FP32 = 0, PD_FP64 = 1 };                      /* pd_config.precision */
 enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1 };  /* pd_request.kernel   */
+/* pd_request.model:
+ *   PD_MODEL_L1  min 1/2||A chi - delta||^2 + lambda ||chi||_1 (see the top),
+ *                with the duality-gap stop rule available;
+ *   PD_MODEL_TV  the full Eq. (1),
+ *                min lambda/2 ||W (A chi - delta)||^2 + ||M G chi||_1,
+ *                by the PD pseudocode with K = [W A; M G] (Sec. II-A):
+ *                  p <- (p + sigma (W A chibar - W delta)) / (1 + sigma/lambda)
+ *                  q <- v / max(1, |v|),  v = q + sigma M G chibar (per voxel)
+ *                  chi' = chi - tau A W p - tau G* M q
+ *                  chibar = chi' + theta (chi' - chi)
+ *                lambda weights the data term here; W (weights) and M (mask)
+ *                are real per-voxel arrays; G is the in-plane forward
+ *                difference divided by the voxel size, zero at the last column
+ *                and row (slices stay independent), with the isotropic
+ *                norm |(g_x, g_y)|.  Runs exactly max_iter iterations. */
+enum { PD_MODEL_L1 = 0, PD_MODEL_TV = 1 };
 
 /* pd_config.flags */
 enum {
@@ -102,7 +119,18 @@ typedef struct {
   const void* delta;   /* field map [nz][ny][nx]; must stay valid and unchanged
                           until the ticket completes                               */
   void* chi;           /* output [nz][ny][nx]; written once, at completion         */
+  int model;           /* PD_MODEL_L1 (0) or PD_MODEL_TV                           */
+  const void* weight;  /* TV model: W [nz][ny][nx] (like delta: valid, unchanged
+                          until completion); non-NULL for PD_MODEL_TV           */
+  const void* mask;    /* TV model: M [nz][ny][nx], same rules                     */
 } pd_request;
+/* TV model specifics: gap_tol must be 0 and lambda > 0 (PD_ERR_ARG otherwise);
+ * check_every is ignored.  Its step condition, tau*sigma*L2 < 1 with
+ *   L2 = max|W|^2 max|D|^2 + max|M|^2 (4/dx^2 + 4/dy^2)  (a bound on ||K||^2),
+ * needs the maxima of W and M, which the library takes on the GPU at
+ * admission: a violation ends the ticket with PD_ERR_STEP and a non-finite
+ * value in delta, W or M with PD_ERR_NONFINITE, before any iteration (chi
+ * then holds zeros).  pd_validate cannot see W and M and does not test it. */
 
 typedef struct {
   pd_status status;    /* PD_OK, PD_ERR_NONFINITE, PD_ERR_CANCELLED or PD_ERR_HIP */
@@ -110,7 +138,8 @@ typedef struct {
   double primal;       /* P    = sum 1/2||A chi - delta||^2 + lambda ||chi||_1     */
   double dual;         /* Dual = sum -1/2 s^2||y||^2 - s <y, delta>,
                           s = min(1, lambda / max|A y|)                            */
-  double rel_gap;      /* (P - Dual) / max(P, 1e-300), FP64 reductions             */
+  double rel_gap;      /* (P - Dual) / max(P, 1e-300), FP64 reductions.
+                          primal, dual and rel_gap are NaN for the TV model       */
   double t_submit, t_start, t_done;   /* seconds on pd_now()'s clock              */
 } pd_result;
 
@@ -164,7 +193,10 @@ double pd_now(void);
  * since the last reset.  kind: 0 = column kernel (forward column FFT, dual
  * prox, inverse column FFT), 1 = row kernel (inverse row FFT, primal prox,
  * over-relaxation, forward row FFT), 2 = resident kernel (a whole step of
- * iterations of square slices kept on chip).  pd_kernel_time_reset clears all. */
+ * iterations of square slices kept on chip), 3 = TV-model column kernel
+ * (forward column FFT, multiply by D, inverse column FFT; two per iteration),
+ * 4 = TV-model row kernels (inverse row FFT, dual or primal update, forward
+ * row FFT; two per iteration).  pd_kernel_time_reset clears all. */
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 

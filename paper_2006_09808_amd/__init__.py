@@ -1,7 +1,8 @@
 """MI355X primal-dual solver for positive-contrast susceptibility MRI.
 
-Wang, Cai et al., arXiv:2006.09808: L1-regularised dipole-kernel
-deconvolution by the first-order primal-dual iteration, slice by slice.  The
+Wang, Cai et al., arXiv:2006.09808: dipole-kernel deconvolution by the
+first-order primal-dual iteration, slice by slice, with an L1 prior on chi or
+the weighted total-variation model of Eq. (1).  The
 solve runs in hand-written HIP kernels for gfx950 behind the C ABI of
 include/pd.h; this package is its Python binding (argument marshalling only).
 """
@@ -10,5 +11,6 @@ from .pdlib import (  # noqa: F401
     make_request, LIB_PATH, EXPORTS, SUPPORTED_SIZES,
     PD_OK, PD_PENDING, PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET,
     PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE,
-    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, PD_FLAG_NO_RESIDENT,
+    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW,
+    PD_FLAG_NO_RESIDENT, PD_MODEL_L1, PD_MODEL_TV,
 )

@@ -139,8 +139,11 @@ struct Layout {
   int P, rows, cols, row_groups, col_groups;
   size_t field;                     // one [P][ny][nx] complex buffer
   size_t off_chi, off_yhat, off_dhat, off_ex, off_ex2, off_prow, off_pcol;
+  // weighted TV model: over-relaxed primal, duals p, q_x, q_y, packed W, M, delta
+  size_t off_chibar, off_p, off_qx, off_qy, off_w, off_m, off_d;
   size_t total;
   bool separate_ex2;
+  bool tv;
 };
 
 Layout layout_of(const pd_request& r, int precision) {
@@ -152,8 +155,24 @@ Layout layout_of(const pd_request& r, int precision) {
   L.row_groups = r.ny / L.rows;
   L.col_groups = r.nx / L.cols;
   L.field = align_up((size_t)L.P * r.nx * r.ny * esz);
-  L.separate_ex2 = r.gap_tol > 0.0;
   size_t o = 0;
+  if (r.model == PD_MODEL_TV) {
+    // all state in the image domain; no gap partials (fixed iteration count)
+    L.tv = true;
+    L.off_chi = o; o += L.field;
+    L.off_chibar = o; o += L.field;
+    L.off_p = o; o += L.field;
+    L.off_qx = o; o += L.field;
+    L.off_qy = o; o += L.field;
+    L.off_w = o; o += L.field;
+    L.off_m = o; o += L.field;
+    L.off_d = o; o += L.field;
+    L.off_ex = o; o += L.field;
+    L.off_ex2 = L.off_ex;
+    L.total = o;
+    return L;
+  }
+  L.separate_ex2 = r.gap_tol > 0.0;
   L.off_chi = o; o += L.field;
   L.off_yhat = o; o += L.field;
   L.off_dhat = o; o += L.field;
@@ -188,12 +207,20 @@ pd_status validate(const pd_request* r, int precision, double* norm_out) {
   if (!isfin(r->gap_tol) || r->gap_tol < 0) return PD_ERR_ARG;
   if (r->gap_tol > 0 && r->check_every < 1) return PD_ERR_ARG;
   if (!r->delta || !r->chi) return PD_ERR_ARG;
+  if (r->model != PD_MODEL_L1 && r->model != PD_MODEL_TV) return PD_ERR_ARG;
+  if (r->model == PD_MODEL_TV) {
+    // lam weights the data term (it divides sigma in the dual prox); the
+    // model runs a fixed number of iterations
+    if (!r->weight || !r->mask || r->gap_tol != 0.0 || !(r->lambda > 0)) return PD_ERR_ARG;
+  }
   if (!isfin(r->tau) || !isfin(r->sigma) || r->tau <= 0 || r->sigma <= 0) return PD_ERR_STEP;
   if (!isfin(r->theta) || r->theta < 0 || r->theta > 1) return PD_ERR_STEP;
   std::vector<double> D;
   dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
   double L = grid_norm(D);
-  if (!(r->tau * r->sigma * L * L < 1.0)) return PD_ERR_STEP;
+  // the TV model's condition also needs max|W| and max|M|: tested on the
+  // device at admission
+  if (r->model == PD_MODEL_L1 && !(r->tau * r->sigma * L * L < 1.0)) return PD_ERR_STEP;
   if (norm_out) *norm_out = L;
   return PD_OK;
 }
@@ -284,12 +311,17 @@ struct Job {
   Table tab{};              // copy of the shared table's device pointers
   int done_iters = 0;
   bool finished = false;
+  double knorm = 0.0;       // max |D| of the request's kernel grid
   pd_result res{};
 };
 
 struct GroupKey {
-  int nx, ny;
-  bool operator<(const GroupKey& o) const { return nx != o.nx ? nx < o.nx : ny < o.ny; }
+  int nx, ny, model;
+  bool operator<(const GroupKey& o) const {
+    if (nx != o.nx) return nx < o.nx;
+    if (ny != o.ny) return ny < o.ny;
+    return model < o.model;
+  }
 };
 
 }  // namespace
@@ -353,9 +385,10 @@ struct pd_ctx {
   // kernel timing
   bool time_kernels = false;
   std::mutex tmu;
-  int64_t t_launches[3] = {0, 0, 0};
-  double t_ms[3] = {0.0, 0.0, 0.0};
-  double t_points[3] = {0.0, 0.0, 0.0};   // iterations x slice-pair points processed
+  static constexpr int kKinds = 5;        // column, row, resident, TV column, TV row
+  int64_t t_launches[kKinds] = {};
+  double t_ms[kKinds] = {};
+  double t_points[kKinds] = {};           // iterations x slice-pair points processed
   std::vector<hipEvent_t> ev_pool;
 };
 
@@ -472,6 +505,23 @@ void fill_vol(pd_ctx* c, const Job& j, Vol& V) {
   V.row_groups = j.L.row_groups;
   V.col_groups = j.L.col_groups;
   V.final_it = -1;
+  V.model = j.req.model;
+  if (j.L.tv) {
+    V.chibar = base + j.L.off_chibar;
+    V.pdual = base + j.L.off_p;
+    V.qx = base + j.L.off_qx;
+    V.qy = base + j.L.off_qy;
+    V.wgt = base + j.L.off_w;
+    V.msk = base + j.L.off_m;
+    V.dpk = base + j.L.off_d;
+    V.user_w = j.req.weight;
+    V.user_m = j.req.mask;
+    V.yhat = V.dhat = nullptr;
+    V.part_row = V.part_col = nullptr;
+  }
+  V.inv_dx = 1.0 / j.req.voxel[0];
+  V.inv_dy = 1.0 / j.req.voxel[1];
+  V.knorm = j.knorm;
 }
 
 // Reserve arena + slot for a queued job; caller holds c->mu.  Returns false
@@ -538,6 +588,11 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
     Job* j = js[k];
     const Range* rg = c->d_ranges + k;
     int P = j->L.P;
+    if (j->L.tv) {   // pack W, M, delta; step condition on the device
+      e = launch_tv_setup(c->d_vols, c->d_ctl, j->slot, (size_t)P * j->req.nx * j->req.ny, c->precision, c->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     // F_x of delta's rows -> ex, then F_y of ex's columns -> dhat
     e = launch_row(j->req.nx, ROW_FWD_PLANAR, j->L.rows, P * j->L.row_groups, j->L.row_groups, c->d_vols, rg, 1,
                    c->d_ctl, 0, c->precision, c->stream);
@@ -561,7 +616,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   bool any_check_only = false;
   for (auto& j : act) {
     if (j->req.max_iter == 0) {
-      any_check_only = true;
+      any_check_only |= !j->L.tv;   // a TV volume with no iteration just retires
       continue;
     }
     int rem = j->req.max_iter - j->done_iters;
@@ -576,10 +631,16 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   int nslot_list = 0;
   bool any_check = false;
   for (auto& j : act) {
-    groups[GroupKey{j->req.nx, j->req.ny}].push_back(j.get());
+    groups[GroupKey{j->req.nx, j->req.ny, j->req.model}].push_back(j.get());
     Vol& V = c->h_vols[j->slot];
     fill_vol(c, *j, V);
-    if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
+    if (j->L.tv) {                  // fixed iteration count, no gap checks
+      int rem = j->req.max_iter - j->done_iters;
+      V.iters = std::min(K, rem);
+      V.done_base = j->done_iters;
+      V.final_it = (rem == V.iters) ? V.iters - 1 : -1;
+      V.check_last = 0;
+    } else if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
       V.iters = 1;
       V.done_base = -1;
       V.final_it = 0;
@@ -602,6 +663,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   struct Launch {
     int nx, ny, rows, cols, rg, cg;
     bool resident;
+    bool tv;                                 // weighted TV model (four launches per iteration)
     int team;
     const ResidentVariant* rv;
     int range_off, nranges, npairs;          // resident: one range table
@@ -618,8 +680,9 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   for (auto& g : groups) {
     int nx = g.first.nx, ny = g.first.ny;
     const pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
+    const bool tv = g.first.model == PD_MODEL_TV;
     const ResidentVariant* rv =
-        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only)
+        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv)
             ? resident_variant(nx, tn.res_variant) : nullptr;
     int team = rv ? rv->team() : 0;
     int maxt = team ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
@@ -654,6 +717,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
       L.nx = nx;
       L.ny = ny;
       L.resident = false;
+      L.tv = tv;
       L.row_off = (int)k;
       int np = 0;
       L.rows = rows_valid(tn.rows, nx, ny, c->precision) ? tn.rows : rows_per_wg(nx, ny, c->precision);
@@ -755,6 +819,26 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
             return launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
                               it, c->precision, c->stream);
           };
+          if (L.tv) {
+            auto col_tv = [&] {
+              return launch_col(L.ny, COL_TV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, c->stream);
+            };
+            auto row_tv = [&](int mode) {
+              return [&, mode] {
+                return launch_row(L.nx, mode, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                                  it, c->precision, c->stream);
+              };
+            };
+            for (int half = 0; half < 2; ++half) {
+              r = with_events ? timed(3, pts, col_tv) : col_tv();
+              if (r != hipSuccess) return r;
+              auto rk = row_tv(half == 0 ? ROW_TV_DUAL : ROW_TV_PRIMAL);
+              r = with_events ? timed(4, pts, rk) : rk();
+              if (r != hipSuccess) return r;
+            }
+            continue;
+          }
           r = with_events ? timed(0, pts, col) : col();
           if (r != hipSuccess) return r;
           r = with_events ? timed(1, pts, row) : row();
@@ -763,7 +847,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
       }
       if (any_check) {
         for (auto& L : launches) {
-          if (L.resident) continue;
+          if (L.resident || L.tv) continue;
           const Range* rcol = c->d_ranges + L.col_off;
           r = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                          K - 1, c->precision, c->stream);
@@ -784,7 +868,8 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
                       std::to_string(c->precision);
     for (auto& L : launches) {
       if (L.resident) continue;
-      sig += "|" + std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
+      sig += "|" + std::string(L.tv ? "tv" : "l1") + std::to_string(L.nx) + "," + std::to_string(L.ny) + "," +
+             std::to_string(L.rows) + "," +
              std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
              std::to_string(L.row_off) + "," + std::to_string(L.col_off);
     }
@@ -922,11 +1007,15 @@ void worker_main(pd_ctx* c) {
           Vol& V = c->h_vols[j->slot];
           // the final check always stops a volume; the cap test only guards
           // against a step that could not run it
-          if (C.stop || (j->req.max_iter > 0 && j->done_iters + V.iters >= j->req.max_iter)) {
+          if (C.stop || ((j->req.max_iter > 0 || j->L.tv) && j->done_iters + V.iters >= j->req.max_iter)) {
             j->res.iterations = C.stop ? C.stop_iter : j->done_iters + V.iters;
-            j->res.primal = C.primal;
-            j->res.dual = C.dual;
-            j->res.rel_gap = C.rel_gap;
+            if (j->L.tv) {   // no duality gap is defined for the TV model
+              j->res.primal = j->res.dual = j->res.rel_gap = std::nan("");
+            } else {
+              j->res.primal = C.primal;
+              j->res.dual = C.dual;
+              j->res.rel_gap = C.rel_gap;
+            }
             j->done_iters = j->res.iterations;
             retired.push_back(j);
             if (j->req.max_iter == 0) {
@@ -949,7 +1038,7 @@ void worker_main(pd_ctx* c) {
     if (!hip_ok(c, e)) continue;
     for (auto& j : retired) {
       const Ctl& C = c->h_ctl[j->slot];
-      finish_job(c, *j, C.status ? PD_ERR_NONFINITE : PD_OK);
+      finish_job(c, *j, C.status == 2 ? PD_ERR_STEP : C.status ? PD_ERR_NONFINITE : PD_OK);
       unreserve(c, *j);
       c->active.erase(std::find(c->active.begin(), c->active.end(), j));
     }
@@ -1087,9 +1176,11 @@ pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* ticket
   std::vector<std::shared_ptr<Job>> js;
   size_t avail = c->arena.size() - align_up(c->ctl_bytes);
   for (int i = 0; i < n; ++i) {
-    pd_status s = validate(&r[i], c->precision, nullptr);
+    double knorm = 0.0;
+    pd_status s = validate(&r[i], c->precision, &knorm);
     if (s != PD_OK) return s;
     auto j = std::make_shared<Job>();
+    j->knorm = knorm;
     j->req = r[i];
     j->L = layout_of(r[i], c->precision);
     j->key = key_of(r[i]);
@@ -1172,6 +1263,7 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
   Job j;
   j.req = *r;
   j.req.gap_tol = 0.0;
+  j.req.model = PD_MODEL_L1;         // the operator alone: no model state
   j.L = layout_of(j.req, c->precision);
   j.L.off_chi = j.L.off_yhat = j.L.off_dhat = j.L.off_ex = j.L.off_ex2 = 0;
   j.L.off_prow = j.L.off_pcol = 0;
@@ -1231,7 +1323,7 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
 }
 
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters) {
-  if (!c || kind < 0 || kind > 2) return PD_ERR_ARG;
+  if (!c || kind < 0 || kind >= pd_ctx::kKinds) return PD_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->tmu);
   if (launches) *launches = c->t_launches[kind];
   if (total_ms) *total_ms = c->t_ms[kind];

@@ -25,8 +25,21 @@ struct Vol {
                       //   sum |yhat|^2, Re sum yhat conj(dhat)
   const void* user_in;   // planar [nz][ny][nx] input (field map / operator input)
   void* user_out;        // planar [nz][ny][nx] output
+  // weighted TV model (Eq. (1)); unused by the L1 model.  All image-domain,
+  // pair-interleaved [P][ny][nx] complex like chi.
+  void* chibar;          // over-relaxed primal
+  void* pdual;           // data-term dual p
+  void* qx;              // gradient dual, x component
+  void* qy;              // gradient dual, y component
+  void* wgt;             // weights W
+  void* msk;             // mask M
+  void* dpk;             // field map delta
+  const void* user_w;    // caller's planar [nz][ny][nx] W and M
+  const void* user_m;
   double tau, sigma, lam, theta;
   double gap_tol;
+  double inv_dx, inv_dy; // 1 / voxel size (TV model's gradient)
+  double knorm;          // max |D| (TV model's step check)
   int nx, ny, nz, P;
   int half_last;      // nz odd: the last pair's imaginary part is padding
   int iters;          // iterations to run in this step (0: idle)
@@ -37,17 +50,25 @@ struct Vol {
   int col_groups;     // column-kernel workgroups per pair
   int check_only;     // max_iter == 0: only the gap of chi_0 = 0 is evaluated
   int check_last;     // gap partials after the step's last iteration
-  int pad0;
+  int model;          // 0: L1 prior on chi, 1: weighted TV (Eq. (1))
 };
 
-// Device-side control/result block of one resident request.
-struct Ctl {
+// Device-side control/result block of one resident request.  16-byte
+// aligned: the blocks of all slots form one array that is zero-filled per slot
+// with 16-byte stores.
+struct alignas(16) Ctl {
   int stop;           // set by the gap reduction; kernels skip stopped volumes
   int stop_iter;      // iterations applied when the last check ran
-  int status;         // 0 ok, 1 non-finite
+  int status;         // 0 ok, 1 non-finite, 2 step condition violated
   int checks;
   double primal, dual, rel_gap, max_ay;
+  // TV model set-up: bit patterns of max|W| and max|M| (non-negative
+  // doubles order like their bits), and a non-finite-input flag
+  unsigned long long wmax_bits, mmax_bits;
+  int bad_input;
+  int pad;
 };
+static_assert(sizeof(Ctl) % 16 == 0, "Ctl entries must stay 16-byte aligned");
 
 // One volume's share of a launch: workgroups [first, next range's first)
 // belong to volume `slot`, `groups` consecutive workgroups per pair,
@@ -96,8 +117,8 @@ __device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int 
   find_work_b(ranges, nranges, groups, (int)blockIdx.x, slot, pair, g);
 }
 
-enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3 };
-enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2 };
+enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3, COL_TV = 4 };
+enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2, ROW_TV_DUAL = 3, ROW_TV_PRIMAL = 4 };
 
 constexpr int kThreads = 256;
 
@@ -118,6 +139,10 @@ hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl
 hipError_t launch_store_chi(const Vol* vols, int slot, size_t npairs_pts, int precision,
                             hipStream_t st);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// TV model set-up of one volume: pack W, M and delta into the pair layout,
+// record max|W|, max|M| and non-finite inputs in ctl[slot], then test the
+// step condition and stop the volume (status 1 or 2) if it fails.
+hipError_t launch_tv_setup(const Vol* vols, Ctl* ctl, int slot, size_t npair_pts, int precision, hipStream_t st);
 
 // Resident (multi-iteration, cooperative) launch for square n x n slices.
 // resident_team(n) is the workgroups per pair (0: no resident kernel for n);

@@ -80,6 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     if (ctl[slot].stop || it >= V.iters || V.check_only) return;
   } else if constexpr (MODE == COL_CHECK) {
     if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
+  } else if constexpr (MODE == COL_TV) {
+    if (ctl[slot].stop || it >= V.iters) return;
   }
   const int nx = V.nx;
   const int c0 = g * S;
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
             b[q][r] = mk(dn * yn.x, dn * yn.y);
           }
         }
-    } else {  // COL_APPLY: multiply by D / (nx ny)
+    } else {  // COL_APPLY, COL_TV: multiply by D / (nx ny)
 #pragma unroll
       for (int q = 0; q < F::template nq<QB>(); ++q)
 #pragma unroll
@@ -337,6 +339,12 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   }
 }
 
+}  // namespace pdk
+
+#include "pd_tv_row.hpp"
+
+namespace pdk {
+
 // ---------------------------------------------------------------------------
 // per-length launchers
 // ---------------------------------------------------------------------------
@@ -349,6 +357,7 @@ hipError_t launch_col_t(int mode, int grid, int groups, const Vol* vols, const R
     case COL_CHECK: hipLaunchKernelGGL((k_col<T, N, S, COL_CHECK>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case COL_SETUP: hipLaunchKernelGGL((k_col<T, N, S, COL_SETUP>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case COL_APPLY: hipLaunchKernelGGL((k_col<T, N, S, COL_APPLY>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_TV: hipLaunchKernelGGL((k_col<T, N, S, COL_TV>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -362,6 +371,8 @@ hipError_t launch_row_t(int mode, int grid, int groups, const Vol* vols, const R
     case ROW_ITER: hipLaunchKernelGGL((k_row<T, N, S, ROW_ITER>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case ROW_FWD_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_FWD_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case ROW_INV_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_INV_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV_DUAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_DUAL>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV_PRIMAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_PRIMAL>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

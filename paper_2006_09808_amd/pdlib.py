@@ -18,8 +18,9 @@ PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET = -1, -2, -3, -4
 PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE = -5, -6, -7, -8, -9
 PD_FP32, PD_FP64 = 0, 1
 PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY = 0, 1
+PD_MODEL_L1, PD_MODEL_TV = 0, 1
 PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
-KIND_COLUMN, KIND_ROW, KIND_RESIDENT = 0, 1, 2
+KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW = 0, 1, 2, 3, 4
 
 SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
 
@@ -43,7 +44,8 @@ class PdRequest(ctypes.Structure):
                 ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("theta", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("gap_tol", ctypes.c_double), ("check_every", ctypes.c_int),
-                ("delta", ctypes.c_void_p), ("chi", ctypes.c_void_p)]
+                ("delta", ctypes.c_void_p), ("chi", ctypes.c_void_p),
+                ("model", ctypes.c_int), ("weight", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
 
 
 class PdTuneEntry(ctypes.Structure):
@@ -121,7 +123,7 @@ def now():
 
 def make_request(nx, ny, nz, delta_ptr=0, chi_ptr=0, lam=1e-3, tau=1.4, sigma=1.4, theta=1.0,
                  max_iter=200, gap_tol=0.0, check_every=10, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0),
-                 kernel="dipole"):
+                 kernel="dipole", model="l1", weight_ptr=0, mask_ptr=0):
     r = PdRequest()
     r.nx, r.ny, r.nz = int(nx), int(ny), int(nz)
     r.b0 = (ctypes.c_double * 3)(*[float(v) for v in b0])
@@ -131,6 +133,8 @@ def make_request(nx, ny, nz, delta_ptr=0, chi_ptr=0, lam=1e-3, tau=1.4, sigma=1.
     r.lam, r.tau, r.sigma, r.theta = float(lam), float(tau), float(sigma), float(theta)
     r.max_iter, r.gap_tol, r.check_every = int(max_iter), float(gap_tol), int(check_every)
     r.delta, r.chi = int(delta_ptr) or None, int(chi_ptr) or None
+    r.model = {"l1": PD_MODEL_L1, "tv": PD_MODEL_TV}[model] if isinstance(model, str) else int(model)
+    r.weight, r.mask = int(weight_ptr) or None, int(mask_ptr) or None
     return r
 
 
@@ -209,7 +213,9 @@ class Solver:
         return t
 
     def submit(self, jobs):
-        """jobs: list of (delta, chi, params).  Returns tickets."""
+        """jobs: list of (delta, chi, params).  Returns tickets.  For the
+        weighted TV model, params holds model="tv" and the device tensors
+        weight (W) and mask (M) of delta's shape."""
         torch = self._torch
         reqs = (PdRequest * len(jobs))()
         keep = []
@@ -218,9 +224,19 @@ class Solver:
             self._check_tensor(chi, "chi")
             if delta.shape != chi.shape:
                 raise ValueError("delta and chi shapes differ")
+            params = dict(params)
+            extra = []
+            for key in ("weight", "mask"):
+                t = params.pop(key, None)
+                if t is not None:
+                    self._check_tensor(t, key)
+                    if t.shape != delta.shape:
+                        raise ValueError("%s and delta shapes differ" % key)
+                    params[key + "_ptr"] = t.data_ptr()
+                    extra.append(t)
             nz, ny, nx = delta.shape
             reqs[i] = make_request(nx, ny, nz, delta.data_ptr(), chi.data_ptr(), **params)
-            keep.append((delta, chi))
+            keep.append((delta, chi) + tuple(extra))
         # inputs written by torch on the caller's stream must be complete
         torch.cuda.current_stream(self.device).synchronize()
         tickets = (ctypes.c_uint64 * len(jobs))()

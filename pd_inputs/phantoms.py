@@ -214,3 +214,64 @@ def random_stack(seed, nz, ny, nx, rho=0.01, **params):
     chi = device_stack(rng, nz, ny, nx)
     eta = rng.standard_normal(chi.shape)
     return Workload(chi, eta, rho, name="stack_%dx%dx%d" % (nx, ny, nz), **params)
+
+
+# ---------------------------------------------------------------------------
+# Weighted-TV model inputs (Eq. (1)): weights W and a mask M beside the
+# ground truth.  W stands in for a magnitude-derived weight (about 1 in
+# tissue, lower inside each device's signal void); M is 1 inside an
+# elliptical field of view covering most of the slice, 0 outside.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class TvWorkload:
+    chi_true: np.ndarray            # float64 [nz, ny, nx], ppm
+    eta: np.ndarray                 # float64 [nz, ny, nx], standard normal
+    rho: float
+    weight: np.ndarray              # float64 [nz, ny, nx], in [0.2, 1]
+    mask: np.ndarray                # float64 [nz, ny, nx], 0 or 1
+    lam: float = 100.0              # weight of the data term
+    tau: float = 0.34
+    sigma: float = 0.34
+    theta: float = 1.0
+    max_iter: int = 200
+    b0: tuple = B0_Y
+    voxel: tuple = (1.0, 1.0)
+    name: str = ""
+
+    @property
+    def shape(self):
+        return self.chi_true.shape
+
+    def solver_params(self):
+        """Scalar parameters; W and M travel as arrays beside them."""
+        return dict(lam=self.lam, tau=self.tau, sigma=self.sigma, theta=self.theta,
+                    max_iter=self.max_iter, b0=self.b0, voxel=self.voxel)
+
+
+def weight_and_mask(chi_true, void_scale=2.0):
+    """W = 1 - 0.8 exp(-d^2 / (2 s^2)) with d the distance to the nearest
+    device voxel (|chi| > 50 ppm) in-plane and s = void_scale voxels; M = 1
+    inside the ellipse with semi-axes 0.45 nx, 0.45 ny about the centre."""
+    from scipy.ndimage import distance_transform_edt
+    nz, ny, nx = chi_true.shape
+    yy, xx = _grid(ny, nx)
+    w = np.ones((nz, ny, nx))
+    for z in range(nz):
+        dev = np.abs(chi_true[z]) > 50.0
+        if not dev.any():
+            continue
+        d = distance_transform_edt(~dev)
+        w[z] = 1.0 - 0.8 * np.exp(-d * d / (2.0 * void_scale ** 2))
+    ell = ((xx - (nx - 1) / 2.0) / (0.45 * nx)) ** 2 + ((yy - (ny - 1) / 2.0) / (0.45 * ny)) ** 2 <= 1.0
+    m = np.broadcast_to(ell.astype(np.float64), (nz, ny, nx)).copy()
+    return w, m
+
+
+def tv_stack(seed, nz, ny, nx, rho=0.01, **params):
+    """Device stack (as the batched workload) with its W and M."""
+    rng = np.random.default_rng(seed)
+    chi = device_stack(rng, nz, ny, nx)
+    eta = rng.standard_normal(chi.shape)
+    w, m = weight_and_mask(chi)
+    return TvWorkload(chi, eta, rho, w, m, name="tv_%dx%dx%d" % (nx, ny, nz), **params)

@@ -111,3 +111,60 @@ def test_create_without_gpu_reports_no_device():
     ctx = ctypes.c_void_p()
     assert lib.pd_create(ctypes.byref(cfg), ctypes.byref(ctx)) == pd.PD_ERR_NODEVICE
     assert lib.pd_destroy(None) == pd.PD_OK
+
+
+def test_tv_model_request_rules():
+    tv = dict(model="tv", weight_ptr=3, mask_ptr=4, lam=100.0, tau=0.3, sigma=0.3)
+    # the TV model's arena state: 9 complex [P][ny][nx] fields, no gap partials
+    nb = pd.validate(64, 64, 3, **tv)
+    assert nb >= 9 * 2 * 64 * 64 * 8
+    # its step condition needs max|W| and max|M| (tested on the device), so
+    # host validation accepts steps the L1 model's check would refuse
+    pd.validate(64, 64, 1, **dict(tv, tau=2.0, sigma=2.0))
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, **dict(tv, gap_tol=1e-4))
+    assert e.value.status == pd.PD_ERR_ARG
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, **dict(tv, weight_ptr=0))
+    assert e.value.status == pd.PD_ERR_ARG
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, **dict(tv, mask_ptr=0))
+    assert e.value.status == pd.PD_ERR_ARG
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, **dict(tv, lam=0.0))
+    assert e.value.status == pd.PD_ERR_ARG
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, **dict(tv, theta=1.5))
+    assert e.value.status == pd.PD_ERR_STEP
+    with pytest.raises(pd.PdError) as e:
+        pd.validate(64, 64, 1, model=7)
+    assert e.value.status == pd.PD_ERR_ARG
+
+
+def test_ctypes_structs_match_the_c_layout(tmp_path):
+    # compile a probe against pd.h with the host C compiler and compare every
+    # field offset and struct size with the binding's ctypes declarations
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"pd_config": pd.pdlib.PdConfig, "pd_request": pd.pdlib.PdRequest,
+               "pd_result": pd.pdlib.PdResult, "pd_tune_entry": pd.pdlib.PdTuneEntry}
+    c_names = {"lam": "lambda"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pd.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (sname, sname))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (sname, fname, sname, c_names.get(fname, fname)))
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for sname, cls in structs.items():
+        assert got[(sname, "size")] == ctypes.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert got[(sname, fname)] == getattr(cls, fname).offset, (sname, fname)

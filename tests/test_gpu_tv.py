@@ -1,0 +1,187 @@
+"""GPU parity of the weighted TV model (Eq. (1)) through the C ABI against
+the FP64 TV oracle.
+
+Inputs are seeded device stacks with magnitude-like weights W and an
+elliptical mask M; the field map is made by the oracle's forward operator and
+rounded to FP32, and the same FP32 delta, W and M go to both sides.  Bar:
+relative L2 error on chi <= 1e-4 after a fixed iteration count (FP32 GPU
+arithmetic against FP64), <= 1e-10 for the FP64 GPU build.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pd_inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def solver(torch_mod):
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0)
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def solver64(torch_mod):
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0, precision="fp64")
+    yield s
+    s.close()
+
+
+def make_tv_case(seed, nz, ny, nx, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), iters=40, lam=100.0):
+    w = pd_inputs.tv_stack(seed, nz, ny, nx, max_iter=iters, lam=lam, b0=b0, voxel=voxel)
+    # steps inside the bound tau sigma (max|W|^2 max|D|^2 + max|M|^2 (4/dx^2 + 4/dy^2)) < 1
+    D = oracle.dipole_kernel(nx, ny, b0, voxel)
+    L2 = oracle.kernel_norm(D) ** 2 + oracle.grad_norm_bound(voxel)
+    w.tau = w.sigma = 0.95 / np.sqrt(L2)
+    field = oracle.forward(w.chi_true, b0=b0, voxel=voxel)
+    delta = pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)
+    return w, delta, w.weight.astype(np.float32), w.mask.astype(np.float32)
+
+
+def to_dev(torch, a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dtype=dtype)
+
+
+def gpu_tv(solver, torch, delta, W, M, dtype=None, **params):
+    dtype = dtype or torch.float32
+    d, wt, mt = (to_dev(torch, a, dtype) for a in (delta, W, M))
+    (t,) = solver.submit([(d, torch.empty_like(d), dict(params, model="tv", weight=wt, mask=mt))])
+    info = solver.poll(t, -1)
+    return info, t
+
+
+def gpu_tv_solve(solver, torch, delta, W, M, dtype=None, **params):
+    dtype = dtype or torch.float32
+    d, wt, mt = (to_dev(torch, a, dtype) for a in (delta, W, M))
+    chi = torch.empty_like(d)
+    (t,) = solver.submit([(d, chi, dict(params, model="tv", weight=wt, mask=mt))])
+    info = solver.poll(t, -1)
+    return chi.cpu().numpy().astype(np.float64), info
+
+
+TV_CASES = [
+    # (seed, nz, ny, nx, b0, voxel, iters)
+    (11, 2, 16, 16, (0.0, 1.0, 0.0), (1.0, 1.0), 30),
+    (12, 3, 64, 64, (0.0, 1.0, 0.0), (1.0, 1.0), 60),           # odd nz: padded pair
+    (13, 5, 64, 96, (0.3, 0.5, 0.8), (0.8, 1.2), 40),           # rectangular, oblique B0, anisotropic
+    (14, 4, 128, 128, (0.0, 1.0, 0.0), (1.0, 1.0), 50),
+    (15, 2, 192, 96, (1.0, 1.0, 0.0), (1.0, 0.7), 25),
+    (16, 2, 256, 256, (0.0, 1.0, 0.0), (1.0, 1.0), 30),
+    (17, 1, 384, 384, (0.0, 1.0, 0.0), (1.0, 1.0), 8),          # single slice, largest rows
+]
+
+
+@pytest.mark.parametrize("case", TV_CASES, ids=lambda c: "%d-%d-%d-%d" % c[:4])
+def test_tv_matches_oracle_fixed_iterations(solver, torch_mod, case):
+    seed, nz, ny, nx, b0, vox, iters = case
+    _say("tv case nz=%d ny=%d nx=%d iters=%d" % (nz, ny, nx, iters))
+    w, delta, W, M = make_tv_case(seed, nz, ny, nx, b0, vox, iters)
+    sp = w.solver_params()
+    chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
+    assert info["status"] == 0 and info["iterations"] == iters
+    assert np.isnan(info["rel_gap"])
+    ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
+    err = rel_l2(chi, ref)
+    _say("  relL2 %.3e  max-abs %.3e ppm" % (err, float(np.max(np.abs(chi - ref)))))
+    assert err <= REL_TOL
+
+
+@pytest.mark.parametrize("case", [TV_CASES[1], TV_CASES[2]], ids=lambda c: "%d-%d-%d-%d" % c[:4])
+def test_tv_fp64_matches_oracle(solver64, torch_mod, case):
+    seed, nz, ny, nx, b0, vox, iters = case
+    w, delta, W, M = make_tv_case(seed, nz, ny, nx, b0, vox, iters)
+    sp = w.solver_params()
+    chi, info = gpu_tv_solve(solver64, torch_mod, delta.astype(np.float64), W.astype(np.float64),
+                             M.astype(np.float64), dtype=torch_mod.float64, **sp)
+    assert info["status"] == 0
+    ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
+    err = rel_l2(chi, ref)
+    _say("fp64 tv relL2 %.3e" % err)
+    assert err <= 1e-10
+
+
+def test_tv_zero_iterations_give_zero(solver, torch_mod):
+    w, delta, W, M = make_tv_case(21, 3, 32, 32, iters=0)
+    chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **w.solver_params())
+    assert info["status"] == 0 and info["iterations"] == 0
+    assert np.all(chi == 0)
+
+
+def test_tv_step_condition_checked_on_device(solver, torch_mod):
+    import paper_2006_09808_amd as pd
+    w, delta, W, M = make_tv_case(22, 2, 32, 32, iters=20)
+    # W = 3 everywhere: the bound grows by 9 max|D|^2 and the steps violate it
+    info, _ = gpu_tv(solver, torch_mod, delta, np.full_like(W, 3.0), M, **w.solver_params())
+    assert info["status"] == pd.PD_ERR_STEP and info["iterations"] == 0
+    # the same steps with the generated W in [0.2, 1] are fine
+    info, _ = gpu_tv(solver, torch_mod, delta, W, M, **w.solver_params())
+    assert info["status"] == pd.PD_OK and info["iterations"] == 20
+
+
+def test_tv_nonfinite_input_is_reported(solver, torch_mod):
+    import paper_2006_09808_amd as pd
+    w, delta, W, M = make_tv_case(23, 2, 32, 32, iters=10)
+    M = M.copy()
+    M[1, 5, 7] = np.nan
+    info, _ = gpu_tv(solver, torch_mod, delta, W, M, **w.solver_params())
+    assert info["status"] == pd.PD_ERR_NONFINITE and info["iterations"] == 0
+
+
+def test_tv_and_l1_volumes_in_one_batch_equal_their_solo_runs(solver, torch_mod):
+    torch = torch_mod
+    jobs, outs = [], []
+    cases = [make_tv_case(31, 3, 64, 64, iters=37), make_tv_case(32, 2, 128, 128, iters=23)]
+    for w, delta, W, M in cases:
+        d, wt, mt = (to_dev(torch, a, torch.float32) for a in (delta, W, M))
+        chi = torch.empty_like(d)
+        jobs.append((d, chi, dict(w.solver_params(), model="tv", weight=wt, mask=mt)))
+        outs.append(chi)
+    l1 = pd_inputs.random_stack(33, 4, 64, 64, max_iter=50)
+    field = oracle.forward(l1.chi_true)
+    dl1 = to_dev(torch, pd_inputs.make_delta(field, l1.eta, l1.rho).astype(np.float32), torch.float32)
+    chi_l1 = torch.empty_like(dl1)
+    jobs.append((dl1, chi_l1, l1.solver_params()))
+    outs.append(chi_l1)
+    infos = [solver.poll(t, -1) for t in solver.submit(jobs)]
+    assert all(i["status"] == 0 for i in infos)
+    mixed = [o.cpu().numpy() for o in outs]
+    for (d, _, params), ref in zip(jobs, mixed):
+        solo = torch.empty_like(d)
+        (t,) = solver.submit([(d, solo, params)])
+        assert solver.poll(t, -1)["status"] == 0
+        np.testing.assert_array_equal(solo.cpu().numpy(), ref)
+
+
+def test_tv_repeated_solves_are_bitwise_equal(solver, torch_mod):
+    # the second and later runs of the same plan replay a captured HIP graph
+    w, delta, W, M = make_tv_case(41, 4, 96, 96, iters=25)
+    outs = []
+    for _ in range(3):
+        chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **w.solver_params())
+        assert info["status"] == 0
+        outs.append(chi)
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
