@@ -41,7 +41,7 @@ enum {
   PD_OK = 0,
   PD_PENDING = 1,          /* ticket not finished (pd_poll timeout)               */
   PD_ERR_ARG = -1,         /* null pointer, bad enum, non-finite parameter, ...   */
-  PD_ERR_SIZE = -2,        /* nx or ny not in the supported set, nz < 1          */
+  PD_ERR_SIZE = -2,        /* nx or ny not a supported length, nz < 1             */
   PD_ERR_STEP = -3,        /* tau*sigma*max|D|^2 >= 1, theta outside [0, 1], ...
                               (TV model: tau*sigma*L2 >= 1, found at admission)   */
   PD_ERR_BUDGET = -4,      /* request can never fit in the context's arena       */
@@ -105,7 +105,10 @@ typedef struct {
 
 /* One reconstruction: a volume of nz slices of ny x nx voxels (Eq. (1)). */
 typedef struct {
-  int nx, ny, nz;      /* nx, ny in {8,16,24,32,48,64,96,128,192,256,384,512}   */
+  int nx, ny, nz;      /* nx, ny: 8,16,24,32,48,64,96,128,192,256,384,512,768
+                          (direct FFT plans) or any other length 2..384, whose
+                          DFTs run as Bluestein (chirp-z) convolutions on the
+                          smallest direct length >= 2n - 1                      */
   double b0[3];        /* B0 direction in voxel axes (x, y, z); any non-zero scale */
   double voxel[2];     /* in-plane voxel size (dx, dy), any positive unit          */
   int kernel;          /* PD_KERNEL_DIPOLE, or PD_KERNEL_IDENTITY (D = 1)          */

@@ -8,7 +8,7 @@ include/pd.h; this package is its Python binding (argument marshalling only).
 """
 from .pdlib import (  # noqa: F401
     Solver, PdError, load_library, validate, kernel_norm, status_string, now,
-    make_request, LIB_PATH, EXPORTS, SUPPORTED_SIZES,
+    make_request, LIB_PATH, EXPORTS, SUPPORTED_SIZES, MAX_BLUESTEIN,
     PD_OK, PD_PENDING, PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET,
     PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE,
     PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW,

@@ -246,6 +246,7 @@ PD_PLAN(192, 2, 16, 12, 1)
 PD_PLAN(256, 2, 16, 16, 1)
 PD_PLAN(384, 2, 16, 24, 1)
 PD_PLAN(512, 3, 8, 8, 8)
+PD_PLAN(768, 3, 24, 8, 4)
 #undef PD_PLAN
 
 // radix of the i-th executed pass: inverse runs r(0..M-1), forward r(M-1..0)
@@ -370,10 +371,15 @@ struct Fft {
   // j + r N/QL).  in and out may be the same array when QF == QL.  Starts
   // with a barrier-free LDS write, so the caller must have synchronised
   // any earlier LDS readers (call sync_before_reuse()).
+  // Twiddle-table entries the transform reads (tw[m] = exp(-2 pi i m / N)).
+  static constexpr int TW_MAX = N;
+  static __host__ __device__ constexpr int tw_count(int /*len*/) { return N; }
+
   template <int DIR>
   static __device__ __forceinline__ void run(cpx<T> (&in)[nq<QF<DIR>()>()][QF<DIR>()],
                                              cpx<T> (&out)[nq<QL<DIR>()>()][QL<DIR>()],
-                                             cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid) {
+                                             cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid,
+                                             int /*len*/ = N) {
     if constexpr (M == 1) {
 #pragma unroll
       for (int q = 0; q < nq<QF<DIR>()>(); ++q) {
@@ -407,5 +413,85 @@ struct Fft {
     return nbutter<Q>() % NT == 0 || w < nbutter<Q>();
   }
 };
+
+// ---------------------------------------------------------------------------
+// Bluestein (chirp-z) engine: a length-`len` DFT of any len <= (M + 1) / 2,
+// computed with two length-M transforms of the engine above.  With the chirp
+// c_n = exp(-i pi n^2 / len),
+//     X_k = c_k sum_n (x_n c_n) conj(c_(k-n)),
+// a linear convolution that a cyclic one of length M >= 2 len - 1 computes
+// exactly: X = c . F_M^-1( F_M(c . x, zero-padded) . B ), B = F_M(b) / M with
+// b_m = conj(c_m) for |m| < len (indices mod M) and 0 elsewhere.  The inverse
+// transform conjugates every chirp (its B is F_M(c) / M).  Input and output
+// use the same register layout (the forward length-M transform's first-pass
+// positions); positions n >= len are padding: zero on input, ignored on output.
+//
+// Table `tw` (staged in LDS): [M twiddles of length M][len chirp values]
+// [M entries of B for the forward DFT][M entries of B for the inverse DFT].
+// ---------------------------------------------------------------------------
+template <typename T, int M, int S, int NT, bool COLS>
+struct Blue {
+  using F0 = Fft<T, M, S, NT, COLS>;
+  static constexpr int kNT = NT;
+  static constexpr int LDS_ELEMS = F0::LDS_ELEMS;
+  static constexpr int L0 = F0::template QF<-1>();   // forward first-pass radix
+  static constexpr int L1 = F0::template QL<-1>();   // forward last-pass radix
+  template <int DIR>
+  static constexpr int QF() { return L0; }
+  template <int DIR>
+  static constexpr int QL() { return L0; }
+  template <int Q>
+  static constexpr int nq() { return F0::template nq<Q>(); }
+  static constexpr int TW_MAX = M + (M + 1) / 2 + 2 * M;
+  static __host__ __device__ constexpr int tw_count(int len) { return 3 * M + len; }
+
+  template <int Q>
+  static __device__ __forceinline__ bool pos(int tid, int q, int r, int& s, int& n) {
+    return F0::template pos<Q>(tid, q, r, s, n);
+  }
+
+  template <int DIR>
+  static __device__ __forceinline__ void run(cpx<T> (&in)[nq<L0>()][L0], cpx<T> (&out)[nq<L0>()][L0], cpx<T>* lds,
+                                             const cpx<T>* __restrict__ tw, int tid, int len) {
+    const cpx<T>* __restrict__ chirp = tw + M;
+    const cpx<T>* __restrict__ bh = tw + M + len + (DIR < 0 ? 0 : M);
+    // a_n = x_n c_n (conj(c_n) for the inverse), zero beyond len
+#pragma unroll
+    for (int q = 0; q < nq<L0>(); ++q)
+#pragma unroll
+      for (int r = 0; r < L0; ++r) {
+        int s, n;
+        const bool ok = F0::template pos<L0>(tid, q, r, s, n);
+        if (ok && n < len) in[q][r] = DIR < 0 ? cmul(in[q][r], chirp[n]) : cmulc(in[q][r], chirp[n]);
+        else in[q][r] = mk((T)0, (T)0);
+      }
+    cpx<T> mid[nq<L1>()][L1];
+    F0::template run<-1>(in, mid, lds, tw, tid);
+#pragma unroll
+    for (int q = 0; q < nq<L1>(); ++q)
+#pragma unroll
+      for (int r = 0; r < L1; ++r) {
+        int s, k;
+        if (F0::template pos<L1>(tid, q, r, s, k)) mid[q][r] = cmul(mid[q][r], bh[k]);
+      }
+    F0::sync_before_reuse();
+    F0::template run<+1>(mid, out, lds, tw, tid);
+#pragma unroll
+    for (int q = 0; q < nq<L0>(); ++q)
+#pragma unroll
+      for (int r = 0; r < L0; ++r) {
+        int s, n;
+        if (F0::template pos<L0>(tid, q, r, s, n) && n < len)
+          out[q][r] = DIR < 0 ? cmul(out[q][r], chirp[n]) : cmulc(out[q][r], chirp[n]);
+      }
+  }
+
+  static __device__ __forceinline__ void sync_before_reuse() { __syncthreads(); }
+};
+
+// Engine of a kernel's transform axis: EXT < 2 the plain length-N engine,
+// EXT == 2 the Bluestein engine on length-N transforms.
+template <typename T, int N, int S, int NT, bool COLS, int EXT>
+using AxisFft = std::conditional_t<EXT == 2, Blue<T, N, S, NT, COLS>, Fft<T, N, S, NT, COLS>>;
 
 }  // namespace pdk

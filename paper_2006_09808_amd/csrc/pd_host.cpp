@@ -106,6 +106,70 @@ void twiddles(int n, std::vector<double>& re, std::vector<double>& im) {
   }
 }
 
+// One axis of a slice: lengths with a direct plan are transformed as they
+// are; any other length n (2 <= n <= 384) by the Bluestein engine on
+// transforms of length blue_len(n).
+inline bool axis_ok(int n) { return size_supported(n) || blue_len(n) > 0; }
+inline bool axis_blue(int n) { return !size_supported(n); }
+inline int axis_phys(int n) { return axis_blue(n) ? blue_len(n) : n; }
+// twiddle-table entries of the axis: the length-n twiddles, or for Bluestein
+// [M twiddles][n chirp values][M forward kernel][M inverse kernel]
+inline size_t axis_tw_entries(int n) { return axis_blue(n) ? (size_t)3 * blue_len(n) + n : (size_t)n; }
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+// kernel variant for transforms along an axis of length n in tiles of `tile`
+// sequences out of `other`: 2 Bluestein, 1 partial last tile, 0 plain
+inline int axis_ext(int n, int other, int tile) { return axis_blue(n) ? 2 : (other % tile ? 1 : 0); }
+
+// Bluestein table of a length-n axis on length-M transforms, interleaved
+// (re, im): [M twiddles exp(-2 pi i m / M)][n chirp values c_k =
+// exp(-i pi k^2 / n)][B_fwd][B_inv], B = F_M(b) / M with b_m = conj(c_|m|)
+// (forward) or c_|m| (inverse) for |m| < n, indices mod M, 0 elsewhere.
+// All in FP64 with exact integer argument reduction.
+void bluestein_table(int n, int M, std::vector<double>& out) {
+  const double pi = 3.14159265358979323846264338327950288;
+  std::vector<double> re, im;
+  twiddles(M, re, im);
+  out.assign(2 * ((size_t)3 * M + n), 0.0);
+  for (int m = 0; m < M; ++m) {
+    out[2 * m] = re[m];
+    out[2 * m + 1] = im[m];
+  }
+  std::vector<double> cr(n), ci(n);
+  for (int q = 0; q < n; ++q) {
+    long long r = ((long long)q * q) % (2LL * n);
+    double a = pi * (double)r / (double)n;
+    cr[q] = std::cos(a);
+    ci[q] = -std::sin(a);
+    out[2 * ((size_t)M + q)] = cr[q];
+    out[2 * ((size_t)M + q) + 1] = ci[q];
+  }
+  for (int dir = 0; dir < 2; ++dir) {
+    std::vector<double> br(M, 0.0), bi(M, 0.0);
+    const double sgn = dir == 0 ? -1.0 : 1.0;   // forward: conj(c); inverse: c
+    for (int q = 0; q < n; ++q) {
+      br[q] = cr[q];
+      bi[q] = sgn * ci[q];
+      if (q > 0) {
+        br[M - q] = cr[q];
+        bi[M - q] = sgn * ci[q];
+      }
+    }
+    const size_t off = (size_t)M + n + (size_t)dir * M;
+    for (int kk = 0; kk < M; ++kk) {
+      double sr = 0.0, si = 0.0;
+      for (int m = 0; m < M; ++m) {
+        long long e = ((long long)m * kk) % M;
+        double w = -2.0 * pi * (double)e / (double)M;
+        double wr = std::cos(w), wi = std::sin(w);
+        sr += br[m] * wr - bi[m] * wi;
+        si += br[m] * wi + bi[m] * wr;
+      }
+      out[2 * (off + kk)] = sr / M;
+      out[2 * (off + kk) + 1] = si / M;
+    }
+  }
+}
+
 // work decomposition (must match the kernel instantiations)
 int row_group_big(int nx) {   // the larger instantiated FP32 row group of length-nx rows
   int s = 8;
@@ -113,30 +177,33 @@ int row_group_big(int nx) {   // the larger instantiated FP32 row group of lengt
   return s;
 }
 int rows_per_wg(int nx, int ny, int precision) {
-  if (precision == PD_FP64) return 8;
+  if (precision == PD_FP64 || axis_blue(nx)) return 8;
   int s = row_group_big(nx);
   return (ny % s == 0) ? s : 8;
 }
-int cols_per_wg(int nx, int /*ny*/, int precision) {
-  if (precision == PD_FP64) return 8;
+int cols_per_wg(int nx, int ny, int precision) {
+  if (precision == PD_FP64 || axis_blue(ny) || ny > 512) return 8;
   return (nx % 16 == 0) ? 16 : 8;
 }
 
-// instantiated tile sizes of the two-launch kernels (FP32): rows per row-kernel
-// workgroup in {8, default}, columns per column-kernel workgroup in {8, 16}
+// instantiated tile sizes of the two-launch kernels: FP32 plain transforms
+// over whole tiles have rows per row-kernel workgroup in {8, default} and
+// columns per column-kernel workgroup in {8, 16} (8 for columns of 768);
+// every other case (FP64, Bluestein, partial last tile) has tiles of 8
 bool rows_valid(int r, int nx, int ny, int precision) {
-  if (r <= 0 || ny % r) return false;
-  if (precision == PD_FP64) return r == 8;
+  if (r <= 0) return false;
+  if (precision == PD_FP64 || axis_blue(nx) || ny % r) return r == 8;
   return r == 8 || r == row_group_big(nx);
 }
-bool cols_valid(int cl, int nx, int precision) {
-  if (cl <= 0 || nx % cl) return false;
-  if (precision == PD_FP64) return cl == 8;
+bool cols_valid(int cl, int nx, int ny, int precision) {
+  if (cl <= 0) return false;
+  if (precision == PD_FP64 || axis_blue(ny) || ny > 512 || nx % cl) return cl == 8;
   return cl == 8 || cl == 16;
 }
 
 struct Layout {
   int P, rows, cols, row_groups, col_groups;
+  int ext_row, ext_col;             // kernel variants of the default tiles
   size_t field;                     // one [P][ny][nx] complex buffer
   size_t off_chi, off_yhat, off_dhat, off_ex, off_ex2, off_prow, off_pcol;
   // weighted TV model: over-relaxed primal, duals p, q_x, q_y, packed W, M, delta
@@ -152,8 +219,10 @@ Layout layout_of(const pd_request& r, int precision) {
   L.P = (r.nz + 1) / 2;
   L.rows = rows_per_wg(r.nx, r.ny, precision);
   L.cols = cols_per_wg(r.nx, r.ny, precision);
-  L.row_groups = r.ny / L.rows;
-  L.col_groups = r.nx / L.cols;
+  L.row_groups = ceil_div(r.ny, L.rows);
+  L.col_groups = ceil_div(r.nx, L.cols);
+  L.ext_row = axis_ext(r.nx, r.ny, L.rows);
+  L.ext_col = axis_ext(r.ny, r.nx, L.cols);
   L.field = align_up((size_t)L.P * r.nx * r.ny * esz);
   size_t o = 0;
   if (r.model == PD_MODEL_TV) {
@@ -181,7 +250,7 @@ Layout layout_of(const pd_request& r, int precision) {
   // gap partials: one entry per workgroup of any tile choice of the
   // two-launch kernels (8 rows or columns per workgroup at the least) or of
   // any resident team (at most 32 workgroups per pair)
-  size_t pg = (size_t)std::max(std::max(r.ny / 8, r.nx / 8), 32);
+  size_t pg = (size_t)std::max(std::max(ceil_div(r.ny, 8), ceil_div(r.nx, 8)), 32);
   L.off_prow = o; o += align_up((size_t)L.P * pg * 2 * sizeof(double));
   L.off_pcol = o; o += align_up((size_t)L.P * pg * 3 * sizeof(double));
   L.total = o;
@@ -190,13 +259,13 @@ Layout layout_of(const pd_request& r, int precision) {
 
 size_t table_bytes(int nx, int ny, int precision) {
   size_t t = precision == PD_FP64 ? 8 : 4;
-  return align_up((size_t)nx * ny * t) + align_up((size_t)nx * 2 * t) + align_up((size_t)ny * 2 * t);
+  return align_up((size_t)nx * ny * t) + align_up(axis_tw_entries(nx) * 2 * t) + align_up(axis_tw_entries(ny) * 2 * t);
 }
 
 pd_status validate(const pd_request* r, int precision, double* norm_out) {
   if (!r) return PD_ERR_ARG;
   if (precision != PD_FP32 && precision != PD_FP64) return PD_ERR_ARG;
-  if (!size_supported(r->nx) || !size_supported(r->ny) || r->nz < 1) return PD_ERR_SIZE;
+  if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
   if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
   double bu[3];
   if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
@@ -415,7 +484,7 @@ Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
   char* p = c->arena.ptr(t.off);
   t.d = p;
   t.twx = p + align_up((size_t)k.nx * k.ny * tsz);
-  t.twy = (char*)t.twx + align_up((size_t)k.nx * 2 * tsz);
+  t.twy = (char*)t.twx + align_up(axis_tw_entries(k.nx) * 2 * tsz);
   t.refs = 1;
   t.uploaded = false;
   *fresh = true;
@@ -439,13 +508,22 @@ hipError_t upload_table(pd_ctx* c, const TableKey& k, const Table& t) {
   for (size_t i = 0; i < D.size(); ++i) hd[i] = (T)D[i];
   hipError_t e = hipMemcpyAsync(t.d, hd.data(), hd.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
+  std::vector<std::vector<T>> tws(2);
   for (int axis = 0; axis < 2; ++axis) {
     int n = axis == 0 ? k.nx : k.ny;
-    twiddles(n, re, im);
-    std::vector<T> tw(2 * (size_t)n);
-    for (int m = 0; m < n; ++m) {
-      tw[2 * m] = (T)re[m];
-      tw[2 * m + 1] = (T)im[m];
+    std::vector<T>& tw = tws[axis];
+    if (!axis_blue(n)) {
+      twiddles(n, re, im);
+      tw.resize(2 * (size_t)n);
+      for (int m = 0; m < n; ++m) {
+        tw[2 * m] = (T)re[m];
+        tw[2 * m + 1] = (T)im[m];
+      }
+    } else {
+      std::vector<double> all;
+      bluestein_table(n, blue_len(n), all);
+      tw.resize(all.size());
+      for (size_t m = 0; m < all.size(); ++m) tw[m] = (T)all[m];
     }
     e = hipMemcpyAsync(axis == 0 ? t.twx : t.twy, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice,
                        c->stream);
@@ -594,11 +672,11 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
       continue;
     }
     // F_x of delta's rows -> ex, then F_y of ex's columns -> dhat
-    e = launch_row(j->req.nx, ROW_FWD_PLANAR, j->L.rows, P * j->L.row_groups, j->L.row_groups, c->d_vols, rg, 1,
-                   c->d_ctl, 0, c->precision, c->stream);
+    e = launch_row(axis_phys(j->req.nx), ROW_FWD_PLANAR, j->L.rows, P * j->L.row_groups, j->L.row_groups, c->d_vols,
+                   rg, 1, c->d_ctl, 0, c->precision, j->L.ext_row, c->stream);
     if (e != hipSuccess) return e;
-    e = launch_col(j->req.ny, COL_SETUP, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols, rg, 1,
-                   c->d_ctl, 0, c->precision, c->stream);
+    e = launch_col(axis_phys(j->req.ny), COL_SETUP, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols,
+                   rg, 1, c->d_ctl, 0, c->precision, j->L.ext_col, c->stream);
     if (e != hipSuccess) return e;
     // X'_0 = F_x chibar_0 = 0
     e = launch_zero(c->arena.ptr(j->off) + j->L.off_ex, j->L.field, c->stream);
@@ -664,6 +742,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     int nx, ny, rows, cols, rg, cg;
     bool resident;
     bool tv;                                 // weighted TV model (four launches per iteration)
+    int px, py, er, ec;                      // transform lengths and kernel variants (row, column)
     int team;
     const ResidentVariant* rv;
     int range_off, nranges, npairs;          // resident: one range table
@@ -721,9 +800,13 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
       L.row_off = (int)k;
       int np = 0;
       L.rows = rows_valid(tn.rows, nx, ny, c->precision) ? tn.rows : rows_per_wg(nx, ny, c->precision);
-      L.cols = cols_valid(tn.cols, nx, c->precision) ? tn.cols : cols_per_wg(nx, ny, c->precision);
-      L.rg = ny / L.rows;
-      L.cg = nx / L.cols;
+      L.cols = cols_valid(tn.cols, nx, ny, c->precision) ? tn.cols : cols_per_wg(nx, ny, c->precision);
+      L.rg = ceil_div(ny, L.rows);
+      L.cg = ceil_div(nx, L.cols);
+      L.px = axis_phys(nx);
+      L.py = axis_phys(ny);
+      L.er = axis_ext(nx, ny, L.rows);
+      L.ec = axis_ext(ny, nx, L.cols);
       for (Job* j : g.second) {
         Vol& V = c->h_vols[j->slot];
         V.row_groups = L.rg;
@@ -812,22 +895,22 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
           const Range* rcol = c->d_ranges + L.col_off;
           double pts = (double)L.npairs * L.nx * L.ny;
           auto col = [&] {
-            return launch_col(L.ny, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
-                              it, c->precision, c->stream);
+            return launch_col(L.py, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                              it, c->precision, L.ec, c->stream);
           };
           auto row = [&] {
-            return launch_row(L.nx, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
-                              it, c->precision, c->stream);
+            return launch_row(L.px, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                              it, c->precision, L.er, c->stream);
           };
           if (L.tv) {
             auto col_tv = [&] {
-              return launch_col(L.ny, COL_TV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
-                                it, c->precision, c->stream);
+              return launch_col(L.py, COL_TV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, c->stream);
             };
             auto row_tv = [&](int mode) {
               return [&, mode] {
-                return launch_row(L.nx, mode, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
-                                  it, c->precision, c->stream);
+                return launch_row(L.px, mode, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                                  it, c->precision, L.er, c->stream);
               };
             };
             for (int half = 0; half < 2; ++half) {
@@ -849,8 +932,8 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
         for (auto& L : launches) {
           if (L.resident || L.tv) continue;
           const Range* rcol = c->d_ranges + L.col_off;
-          r = launch_col(L.ny, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
-                         K - 1, c->precision, c->stream);
+          r = launch_col(L.py, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                         K - 1, c->precision, L.ec, c->stream);
           if (r != hipSuccess) return r;
         }
       }
@@ -1081,7 +1164,7 @@ pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes) {
 
 pd_status pd_kernel_norm(const pd_request* r, double* norm) {
   if (!r || !norm) return PD_ERR_ARG;
-  if (!size_supported(r->nx) || !size_supported(r->ny)) return PD_ERR_SIZE;
+  if (!axis_ok(r->nx) || !axis_ok(r->ny)) return PD_ERR_SIZE;
   double bu[3];
   if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
   if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
@@ -1251,7 +1334,7 @@ pd_status pd_destroy(pd_ctx* c) {
 
 pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
   if (!c || !r) return PD_ERR_ARG;
-  if (!size_supported(r->nx) || !size_supported(r->ny) || r->nz < 1) return PD_ERR_SIZE;
+  if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
   if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
   double bu[3];
   if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
@@ -1301,14 +1384,14 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
     if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
     const int P = j.L.P;
     if (e == hipSuccess)
-      e = launch_row(r->nx, ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr, 1,
-                     c->d_ctl, 0, c->precision, c->stream);
+      e = launch_row(axis_phys(r->nx), ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
+                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
     if (e == hipSuccess)
-      e = launch_col(r->ny, COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1, c->d_ctl,
-                     0, c->precision, c->stream);
+      e = launch_col(axis_phys(r->ny), COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                     c->d_ctl, 0, c->precision, j.L.ext_col, c->stream);
     if (e == hipSuccess)
-      e = launch_row(r->nx, ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr, 1,
-                     c->d_ctl, 0, c->precision, c->stream);
+      e = launch_row(axis_phys(r->nx), ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
+                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
     hipError_t e2 = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = e2;
   }
@@ -1345,7 +1428,7 @@ pd_status pd_kernel_time_reset(pd_ctx* c) {
 pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
                   int* n_entries) {
   if (!c || iters < 1 || nz < 1 || max_entries < 0) return PD_ERR_ARG;
-  if (!size_supported(nx) || !size_supported(ny)) return PD_ERR_SIZE;
+  if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
   if (n_entries) *n_entries = 0;
   pd_request r{};
   r.nx = nx;
@@ -1454,20 +1537,22 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
       if (!rows_valid(rows, nx, ny, c->precision)) continue;
       for (int cols : {8, 16}) {
         if (e != hipSuccess) break;
-        if (!cols_valid(cols, nx, c->precision)) continue;
+        if (!cols_valid(cols, nx, ny, c->precision)) continue;
         bool dup = false;
         for (auto& t : all) dup |= t.path == 1 && t.rows == rows && t.cols == cols;
         if (dup) continue;
-        int rg = ny / rows, cg = nx / cols;
+        int rg = ceil_div(ny, rows), cg = ceil_div(nx, cols);
+        const int er = axis_ext(nx, ny, rows), ec = axis_ext(ny, nx, cols);
         if ((e = upload_vol(rg, cg)) != hipSuccess) break;
         double best = 0;
         e = time_it([&] {
           hipError_t r2 = hipSuccess;
           for (int it = 0; it < iters && r2 == hipSuccess; ++it) {
-            r2 = launch_col(ny, COL_ITER, cols, P * cg, cg, c->d_vols, dr, 1, c->d_ctl, it, c->precision, c->stream);
+            r2 = launch_col(axis_phys(ny), COL_ITER, cols, P * cg, cg, c->d_vols, dr, 1, c->d_ctl, it, c->precision,
+                            ec, c->stream);
             if (r2 == hipSuccess)
-              r2 = launch_row(nx, ROW_ITER, rows, P * rg, rg, c->d_vols, dr, 1, c->d_ctl, it, c->precision,
-                              c->stream);
+              r2 = launch_row(axis_phys(nx), ROW_ITER, rows, P * rg, rg, c->d_vols, dr, 1, c->d_ctl, it,
+                              c->precision, er, c->stream);
           }
           return r2;
         }, &best);
@@ -1512,10 +1597,10 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
 
 pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
   if (!c) return PD_ERR_ARG;
-  if (!size_supported(nx) || !size_supported(ny)) return PD_ERR_SIZE;
+  if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
   if (variant >= 0 && !(nx == ny && variant < resident_variant_count(nx))) return PD_ERR_ARG;
   if (rows > 0 && !rows_valid(rows, nx, ny, c->precision)) return PD_ERR_ARG;
-  if (cols > 0 && !cols_valid(cols, nx, c->precision)) return PD_ERR_ARG;
+  if (cols > 0 && !cols_valid(cols, nx, ny, c->precision)) return PD_ERR_ARG;
   std::lock_guard<std::mutex> ex(c->exec_mu);   // between scheduling steps
   std::lock_guard<std::mutex> lk(c->mu);
   pd_ctx::Tuned tn;

@@ -126,14 +126,17 @@ constexpr int kThreads = 256;
 // `cols` is the strip width / `rows` the rows per workgroup, `grid` the number
 // of workgroups and `groups` the workgroups per pair.
 
-bool size_supported(int n);
-int col_strip(int ny, int nx);   // columns per column-kernel workgroup
-int row_group(int nx, int ny);   // rows per row-kernel workgroup
+bool size_supported(int n);    // transform lengths with a direct plan
+// Length of the transforms that carry a Bluestein DFT of length n (the
+// smallest direct length >= 2n - 1), 0 if n is out of range.
+int blue_len(int n);
 
+// `n` is the transform length (for ext == 2, the Bluestein length M), `ext`
+// the kernel variant: 0 plain, 1 partial last tile, 2 Bluestein.
 hipError_t launch_col(int n, int mode, int cols, int grid, int groups, const Vol* vols,
-                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st);
+                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st);
 hipError_t launch_row(int n, int mode, int rows, int grid, int groups, const Vol* vols,
-                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st);
+                      const Range* ranges, int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st);
 hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl, int it,
                          int precision, hipStream_t st);
 hipError_t launch_store_chi(const Vol* vols, int slot, size_t npairs_pts, int precision,

@@ -61,16 +61,20 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], int tid) {
 
 // ---------------------------------------------------------------------------
 // Column kernel: strips of S columns, transforms of length NY.
+// EXT = 0: nx is a multiple of S and the columns have length NY.
+// EXT = 1: as 0, but the last strip may be partial (columns >= nx skipped).
+// EXT = 2: columns of any length ny <= (NY + 1) / 2 through the Bluestein
+//          engine on length-NY transforms; the last strip may be partial.
 // ---------------------------------------------------------------------------
-template <typename T, int NY, int S, int MODE>
+template <typename T, int NY, int S, int MODE, int EXT>
 __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
                                                   const Range* __restrict__ ranges, int nranges,
                                                   Ctl* __restrict__ ctl, int groups, int it) {
-  using F = Fft<T, NY, S, kThreads, true>;
+  using F = AxisFft<T, NY, S, kThreads, true, EXT>;
   constexpr int QA = F::template QF<-1>();  // forward first radix == inverse last radix
   constexpr int QB = F::template QL<-1>();  // forward last radix == inverse first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
-  __shared__ cpx<T> tw_s[NY];
+  __shared__ cpx<T> tw_s[F::TW_MAX];
 
   const int tid = threadIdx.x;
   int slot, pair, g;
@@ -84,9 +88,15 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     if (ctl[slot].stop || it >= V.iters) return;
   }
   const int nx = V.nx;
+  const int len = EXT == 2 ? V.ny : NY;     // true column length
   const int c0 = g * S;
-  const size_t base = (size_t)pair * (size_t)nx * NY;
-  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twy), NY, tid, kThreads);
+  const size_t base = (size_t)pair * (size_t)nx * len;
+  // element (s, n) of the strip exists (always, for EXT == 0)
+  auto inb = [&](int s, int n) -> bool {
+    if constexpr (EXT == 0) return true;
+    else return c0 + s < nx && n < len;
+  };
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twy), F::tw_count(len), tid, kThreads);
   __syncthreads();
   const cpx<T>* tw = tw_s;
   const cpx<T>* __restrict__ src =
@@ -99,9 +109,10 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 #pragma unroll
     for (int r = 0; r < QA; ++r) {
       int s, n;
-      if (F::template pos<QA>(tid, q, r, s, n)) a[q][r] = src[(size_t)n * nx + s];
+      if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
+      if (F::template pos<QA>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)n * nx + s];
     }
-  F::template run<-1>(a, b, lds, tw, tid);
+  F::template run<-1>(a, b, lds, tw, tid, len);
 
   const T* __restrict__ dtab = gmem((const T*)V.dtab) + c0;
   if constexpr (MODE == COL_SETUP) {
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 #pragma unroll
       for (int r = 0; r < QB; ++r) {
         int s, n;
-        if (F::template pos<QB>(tid, q, r, s, n)) dh[(size_t)n * nx + s] = b[q][r];
+        if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) dh[(size_t)n * nx + s] = b[q][r];
       }
     return;
   } else if constexpr (MODE == COL_CHECK) {
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 #pragma unroll
       for (int r = 0; r < QB; ++r) {
         int s, n;
-        if (F::template pos<QB>(tid, q, r, s, n)) {
+        if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) {
           size_t o = (size_t)n * nx + s;
           T d = dtab[(size_t)n * nx + s];
           cpx<T> e = dh[o], y = yh[o];
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     }
     return;
   } else {
-    const T invN = (T)(1.0 / ((double)nx * (double)NY));
+    const T invN = (T)(1.0 / ((double)nx * (double)len));
     if constexpr (MODE == COL_ITER) {
       const T sig = (T)V.sigma;
       const T inv1ps = (T)(1.0 / (1.0 + V.sigma));
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 #pragma unroll
         for (int r = 0; r < QB; ++r) {
           int s, n;
-          if (F::template pos<QB>(tid, q, r, s, n)) {
+          if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) {
             size_t o = (size_t)n * nx + s;
             T d = dtab[o];
             cpx<T> y = yh[o], e = dh[o];
@@ -170,21 +181,21 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 #pragma unroll
         for (int r = 0; r < QB; ++r) {
           int s, n;
-          if (F::template pos<QB>(tid, q, r, s, n)) {
+          if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) {
             T dn = dtab[(size_t)n * nx + s] * invN;
             b[q][r] = mk(dn * b[q][r].x, dn * b[q][r].y);
           }
         }
     }
     F::sync_before_reuse();
-    F::template run<+1>(b, a, lds, tw, tid);
+    F::template run<+1>(b, a, lds, tw, tid, len);
     cpx<T>* dst = gmem((cpx<T>*)V.ex) + base + c0;
 #pragma unroll
     for (int q = 0; q < F::template nq<QA>(); ++q)
 #pragma unroll
       for (int r = 0; r < QA; ++r) {
         int s, n;
-        if (F::template pos<QA>(tid, q, r, s, n)) dst[(size_t)n * nx + s] = a[q][r];
+        if (F::template pos<QA>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)n * nx + s] = a[q][r];
       }
   }
 }
@@ -192,15 +203,17 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 // ---------------------------------------------------------------------------
 // Row kernel: S rows per workgroup, transforms of length NX.
 // ---------------------------------------------------------------------------
-template <typename T, int NX, int S, int MODE>
+// EXT as for the column kernel, along rows: 1 = the last row group may be
+// partial, 2 = rows of any length nx <= (NX + 1) / 2 through Bluestein.
+template <typename T, int NX, int S, int MODE, int EXT>
 __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
                                                   const Range* __restrict__ ranges, int nranges,
                                                   Ctl* __restrict__ ctl, int groups, int it) {
-  using F = Fft<T, NX, S, kThreads, false>;
+  using F = AxisFft<T, NX, S, kThreads, false, EXT>;
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
-  __shared__ cpx<T> tw_s[NX];
+  __shared__ cpx<T> tw_s[F::TW_MAX];
 
   const int tid = threadIdx.x;
   int slot, pair, g;
@@ -210,37 +223,43 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
     if (ctl[slot].stop || it >= V.iters || V.check_only) return;
   }
   const int ny = V.ny;
+  const int len = EXT == 2 ? V.nx : NX;     // true row length (and row stride)
   const int r0 = g * S;
-  const size_t base = (size_t)pair * (size_t)NX * ny + (size_t)r0 * NX;
-  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), NX, tid, kThreads);
+  const size_t base = (size_t)pair * (size_t)len * ny + (size_t)r0 * len;
+  auto inb = [&](int s, int n) -> bool {
+    if constexpr (EXT == 0) return true;
+    else return r0 + s < ny && n < len;
+  };
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), F::tw_count(len), tid, kThreads);
   __syncthreads();
   const cpx<T>* tw = tw_s;
   const bool pad_imag = V.half_last && pair == V.P - 1;
-  const size_t plane = (size_t)NX * ny;
+  const size_t plane = (size_t)len * ny;
 
   cpx<T> a[F::template nq<QI>()][QI];
   cpx<T> b[F::template nq<QO>()][QO];
 
   if constexpr (MODE == ROW_FWD_PLANAR) {
-    const T* __restrict__ in = gmem((const T*)V.user_in) + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+    const T* __restrict__ in = gmem((const T*)V.user_in) + (size_t)(2 * pair) * plane + (size_t)r0 * len;
 #pragma unroll
     for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
       for (int r = 0; r < QO; ++r) {
         int s, n;
-        if (F::template pos<QO>(tid, q, r, s, n)) {
-          size_t o = (size_t)s * NX + n;
+        if constexpr (EXT != 0) b[q][r] = mk((T)0, (T)0);
+        if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
+          size_t o = (size_t)s * len + n;
           b[q][r] = mk(in[o], pad_imag ? (T)0 : in[plane + o]);
         }
       }
-    F::template run<-1>(b, a, lds, tw, tid);
+    F::template run<-1>(b, a, lds, tw, tid, len);
     cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
     for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
       for (int r = 0; r < QI; ++r) {
         int s, n;
-        if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+        if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)s * len + n] = a[q][r];
       }
     return;
   } else {
@@ -250,19 +269,20 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
 #pragma unroll
       for (int r = 0; r < QI; ++r) {
         int s, n;
-        if (F::template pos<QI>(tid, q, r, s, n)) a[q][r] = src[(size_t)s * NX + n];
+        if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
+        if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)s * len + n];
       }
-    F::template run<+1>(a, b, lds, tw, tid);
+    F::template run<+1>(a, b, lds, tw, tid, len);
 
     if constexpr (MODE == ROW_INV_PLANAR) {
-      T* __restrict__ out = gmem((T*)V.user_out) + (size_t)(2 * pair) * plane + (size_t)r0 * NX;
+      T* __restrict__ out = gmem((T*)V.user_out) + (size_t)(2 * pair) * plane + (size_t)r0 * len;
 #pragma unroll
       for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
         for (int r = 0; r < QO; ++r) {
           int s, n;
-          if (F::template pos<QO>(tid, q, r, s, n)) {
-            size_t o = (size_t)s * NX + n;
+          if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
+            size_t o = (size_t)s * len + n;
             out[o] = b[q][r].x;
             if (!pad_imag) out[plane + o] = b[q][r].y;
           }
@@ -276,14 +296,20 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       const bool last = (it == V.final_it);
       cpx<T>* __restrict__ chi = gmem((cpx<T>*)V.chi) + base;
       cpx<T> c[F::template nq<QO>()][QO];
+      if constexpr (EXT != 0) {
+#pragma unroll
+        for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+          for (int r = 0; r < QO; ++r) c[q][r] = mk((T)0, (T)0);
+      }
       double acc[2] = {0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
         for (int r = 0; r < QO; ++r) {
           int s, n;
-          if (F::template pos<QO>(tid, q, r, s, n)) {
-            size_t o = (size_t)s * NX + n;
+          if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
+            size_t o = (size_t)s * len + n;
             cpx<T> x0 = chi[o];
             cpx<T> u = b[q][r];
             T vx = x0.x - tau * u.x, vy = x0.y - tau * u.y;
@@ -313,26 +339,26 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       }
       if (!last) {
         F::sync_before_reuse();
-        F::template run<-1>(b, a, lds, tw, tid);
+        F::template run<-1>(b, a, lds, tw, tid, len);
         cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
           for (int r = 0; r < QI; ++r) {
             int s, n;
-            if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+            if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)s * len + n] = a[q][r];
           }
       }
       if (check) {
         F::sync_before_reuse();
-        F::template run<-1>(c, a, lds, tw, tid);
+        F::template run<-1>(c, a, lds, tw, tid, len);
         cpx<T>* dst = gmem((cpx<T>*)V.ex2) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
           for (int r = 0; r < QI; ++r) {
             int s, n;
-            if (F::template pos<QI>(tid, q, r, s, n)) dst[(size_t)s * NX + n] = a[q][r];
+            if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)s * len + n] = a[q][r];
           }
       }
     }
@@ -348,34 +374,56 @@ namespace pdk {
 // ---------------------------------------------------------------------------
 // per-length launchers
 // ---------------------------------------------------------------------------
-template <int N, typename T, int S>
+template <int N, typename T, int S, int EXT>
 hipError_t launch_col_t(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                         int it, hipStream_t st) {
   dim3 gr(grid), bl(kThreads);
   switch (mode) {
-    case COL_ITER: hipLaunchKernelGGL((k_col<T, N, S, COL_ITER>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case COL_CHECK: hipLaunchKernelGGL((k_col<T, N, S, COL_CHECK>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case COL_SETUP: hipLaunchKernelGGL((k_col<T, N, S, COL_SETUP>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case COL_APPLY: hipLaunchKernelGGL((k_col<T, N, S, COL_APPLY>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case COL_TV: hipLaunchKernelGGL((k_col<T, N, S, COL_TV>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_ITER: hipLaunchKernelGGL((k_col<T, N, S, COL_ITER, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_CHECK: hipLaunchKernelGGL((k_col<T, N, S, COL_CHECK, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_SETUP: hipLaunchKernelGGL((k_col<T, N, S, COL_SETUP, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_APPLY: hipLaunchKernelGGL((k_col<T, N, S, COL_APPLY, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_TV: hipLaunchKernelGGL((k_col<T, N, S, COL_TV, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-template <int N, typename T, int S>
+template <int N, typename T, int S, int EXT>
 hipError_t launch_row_t(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                         int it, hipStream_t st) {
   dim3 gr(grid), bl(kThreads);
   switch (mode) {
-    case ROW_ITER: hipLaunchKernelGGL((k_row<T, N, S, ROW_ITER>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case ROW_FWD_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_FWD_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case ROW_INV_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_INV_PLANAR>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case ROW_TV_DUAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_DUAL>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
-    case ROW_TV_PRIMAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_PRIMAL>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_ITER: hipLaunchKernelGGL((k_row<T, N, S, ROW_ITER, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_FWD_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_FWD_PLANAR, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_INV_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_INV_PLANAR, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV_DUAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_DUAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV_PRIMAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_PRIMAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// EXT (0, 1, 2) from a runtime value
+template <int N, typename T, int S>
+hipError_t launch_col_x(int ext, int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges,
+                        Ctl* ctl, int it, hipStream_t st) {
+  switch (ext) {
+    case 0: return launch_col_t<N, T, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    case 1: return launch_col_t<N, T, S, 1>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    case 2: return launch_col_t<N, T, S, 2>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <int N, typename T, int S>
+hipError_t launch_row_x(int ext, int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges,
+                        Ctl* ctl, int it, hipStream_t st) {
+  switch (ext) {
+    case 0: return launch_row_t<N, T, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    case 1: return launch_row_t<N, T, S, 1>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    case 2: return launch_row_t<N, T, S, 2>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // rows per row-kernel workgroup for length-N rows (FP32): the largest power
@@ -388,30 +436,34 @@ constexpr int row_s_big(int n) {
 
 }  // namespace pdk
 
-// Defines launch_col_<N> / launch_row_<N>.
+// Defines launch_col_<N> / launch_row_<N>: transforms of length N, tile
+// width `cols` / `rows`, EXT `ext` (0: plain; 1: partial last tile; 2:
+// Bluestein transforms of any length <= (N + 1) / 2 on length-N transforms).
+// FP32 EXT 0 has two tile sizes; every other combination uses tiles of 8.
 #define PD_INSTANTIATE(N)                                                                         \
   namespace pdk {                                                                                 \
   hipError_t launch_col_##N(int mode, int cols, int grid, int groups, const Vol* vols,            \
-                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st) { \
+                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision,    \
+                            int ext, hipStream_t st) {                                            \
     if (precision == 1) {                                                                         \
       if (cols != 8) return hipErrorInvalidValue;                                                 \
-      return launch_col_t<N, double, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);            \
+      return launch_col_x<N, double, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     }                                                                                             \
-    if (cols == 16) return launch_col_t<N, float, 16>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
-    if (cols == 8) return launch_col_t<N, float, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);   \
+    if (ext == 0 && cols == 16 && N <= 512)                                                       \
+      return launch_col_t<N, float, (N <= 512 ? 16 : 8), 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (cols == 8) return launch_col_x<N, float, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     return hipErrorInvalidValue;                                                                  \
   }                                                                                               \
   hipError_t launch_row_##N(int mode, int rows, int grid, int groups, const Vol* vols,            \
-                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision, hipStream_t st) { \
+                            const Range* ranges, int nranges, Ctl* ctl, int it, int precision,    \
+                            int ext, hipStream_t st) {                                            \
     if (precision == 1) {                                                                         \
       if (rows != 8) return hipErrorInvalidValue;                                                 \
-      return launch_row_t<N, double, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);            \
+      return launch_row_x<N, double, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     }                                                                                             \
     constexpr int SB = row_s_big(N);                                                              \
-    if (rows == SB) return launch_row_t<N, float, SB>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
-    if constexpr (SB != 8) {                                                                      \
-      if (rows == 8) return launch_row_t<N, float, 8>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
-    }                                                                                             \
+    if (ext == 0 && rows == SB) return launch_row_t<N, float, SB, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (rows == 8) return launch_row_x<N, float, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     return hipErrorInvalidValue;                                                                  \
   }                                                                                               \
   }

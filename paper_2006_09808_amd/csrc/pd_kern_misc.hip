@@ -6,8 +6,8 @@
 namespace pdk {
 
 #define PD_DECL(N)                                                                                   \
-  hipError_t launch_col_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, hipStream_t); \
-  hipError_t launch_row_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, hipStream_t);
+  hipError_t launch_col_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, hipStream_t); \
+  hipError_t launch_row_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, hipStream_t);
 PD_DECL(8)
 PD_DECL(16)
 PD_DECL(24)
@@ -20,6 +20,7 @@ PD_DECL(192)
 PD_DECL(256)
 PD_DECL(384)
 PD_DECL(512)
+PD_DECL(768)
 #undef PD_DECL
 
 #define PD_DECL_RES(N, V)                                                                                   \
@@ -54,32 +55,40 @@ const ResidentVariant* resident_variant(int n, int v) {
 bool size_supported(int n) {
   switch (n) {
     case 8: case 16: case 24: case 32: case 48: case 64: case 96:
-    case 128: case 192: case 256: case 384: case 512:
+    case 128: case 192: case 256: case 384: case 512: case 768:
       return true;
     default:
       return false;
   }
 }
 
+int blue_len(int n) {
+  static const int lens[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768};
+  if (n < 2) return 0;
+  for (int m : lens)
+    if (m >= 2 * n - 1) return m;
+  return 0;
+}
+
 #define PD_CASE(N, KIND) \
-  case N: return launch_##KIND##_##N(mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, st);
+  case N: return launch_##KIND##_##N(mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, st);
 
 hipError_t launch_col(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
-                      int nranges, Ctl* ctl, int it, int precision, hipStream_t st) {
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
   switch (n) {
     PD_CASE(8, col) PD_CASE(16, col) PD_CASE(24, col) PD_CASE(32, col) PD_CASE(48, col)
     PD_CASE(64, col) PD_CASE(96, col) PD_CASE(128, col) PD_CASE(192, col) PD_CASE(256, col)
-    PD_CASE(384, col) PD_CASE(512, col)
+    PD_CASE(384, col) PD_CASE(512, col) PD_CASE(768, col)
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_row(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
-                      int nranges, Ctl* ctl, int it, int precision, hipStream_t st) {
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
   switch (n) {
     PD_CASE(8, row) PD_CASE(16, row) PD_CASE(24, row) PD_CASE(32, row) PD_CASE(48, row)
     PD_CASE(64, row) PD_CASE(96, row) PD_CASE(128, row) PD_CASE(192, row) PD_CASE(256, row)
-    PD_CASE(384, row) PD_CASE(512, row)
+    PD_CASE(384, row) PD_CASE(512, row) PD_CASE(768, row)
     default: return hipErrorInvalidValue;
   }
 }

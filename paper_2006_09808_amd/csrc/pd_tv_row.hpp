@@ -32,15 +32,16 @@
 
 namespace pdk {
 
-template <typename T, int NX, int S, int MODE>
+// EXT as for the L1 model's row kernel (partial last row group; Bluestein rows).
+template <typename T, int NX, int S, int MODE, int EXT>
 __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vols,
                                                      const Range* __restrict__ ranges, int nranges,
                                                      Ctl* __restrict__ ctl, int groups, int it) {
-  using F = Fft<T, NX, S, kThreads, false>;
+  using F = AxisFft<T, NX, S, kThreads, false, EXT>;
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
-  __shared__ cpx<T> tw_s[NX];
+  __shared__ cpx<T> tw_s[F::TW_MAX];
 
   const int tid = threadIdx.x;
   int slot, pair, g;
@@ -48,9 +49,14 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   const Vol& V = vols[slot];
   if (ctl[slot].stop || it >= V.iters) return;
   const int ny = V.ny;
+  const int len = EXT == 2 ? V.nx : NX;     // true row length (and row stride)
   const int r0 = g * S;
-  const size_t base = (size_t)pair * (size_t)NX * ny + (size_t)r0 * NX;
-  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), NX, tid, kThreads);
+  const size_t base = (size_t)pair * (size_t)len * ny + (size_t)r0 * len;
+  auto inb = [&](int s, int n) -> bool {
+    if constexpr (EXT == 0) return true;
+    else return r0 + s < ny && n < len;
+  };
+  stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), F::tw_count(len), tid, kThreads);
   __syncthreads();
   const cpx<T>* tw = tw_s;
 
@@ -62,9 +68,10 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
 #pragma unroll
     for (int r = 0; r < QI; ++r) {
       int s, n;
-      if (F::template pos<QI>(tid, q, r, s, n)) a[q][r] = ex[(size_t)s * NX + n];
+      if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
+      if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) a[q][r] = ex[(size_t)s * len + n];
     }
-  F::template run<+1>(a, b, lds, tw, tid);
+  F::template run<+1>(a, b, lds, tw, tid, len);
 
   const T sig = (T)V.sigma;
   const T idx = (T)V.inv_dx, idy = (T)V.inv_dy;
@@ -83,15 +90,15 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
 #pragma unroll
       for (int r = 0; r < QO; ++r) {
         int s, n;
-        if (F::template pos<QO>(tid, q, r, s, n)) {
-          const ptrdiff_t o = (ptrdiff_t)s * NX + n;
+        if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
+          const ptrdiff_t o = (ptrdiff_t)s * len + n;
           const cpx<T> w = wg[o], d = dl[o], p0 = pd[o], u = b[q][r];
           const cpx<T> pn = mk((p0.x + sig * w.x * (u.x - d.x)) * damp, (p0.y + sig * w.y * (u.y - d.y)) * damp);
           pd[o] = pn;
           // G chibar_n: forward differences, zero at the last column / row
           const cpx<T> c0 = cb[o];
-          const cpx<T> cr = n + 1 < NX ? cb[o + 1] : c0;
-          const cpx<T> cd = r0 + s + 1 < ny ? cb[o + NX] : c0;
+          const cpx<T> cr = n + 1 < len ? cb[o + 1] : c0;
+          const cpx<T> cd = r0 + s + 1 < ny ? cb[o + len] : c0;
           const cpx<T> m = msk[o], qx0 = qxp[o], qy0 = qyp[o];
           const T vxa = qx0.x + sig * m.x * ((cr.x - c0.x) * idx);
           const T vya = qy0.x + sig * m.x * ((cd.x - c0.x) * idy);
@@ -116,15 +123,15 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
 #pragma unroll
       for (int r = 0; r < QO; ++r) {
         int s, n;
-        if (F::template pos<QO>(tid, q, r, s, n)) {
-          const ptrdiff_t o = (ptrdiff_t)s * NX + n;
+        if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
+          const ptrdiff_t o = (ptrdiff_t)s * len + n;
           const int row = r0 + s;
           const cpx<T> x0 = chi[o], u = b[q][r];
           // G* (M q): element i takes +(M q)[i-1] and -(M q)[i] per axis,
           // where i-1 and i are differences G computes
           const cpx<T> m0 = msk[o], qx0 = qxp[o], qy0 = qyp[o];
           T ta = 0, tb = 0;
-          if (n + 1 < NX) {
+          if (n + 1 < len) {
             ta -= m0.x * qx0.x * idx;
             tb -= m0.y * qx0.y * idx;
           }
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
             tb -= m0.y * qy0.y * idy;
           }
           if (row >= 1) {
-            const cpx<T> mu = msk[o - NX], qu = qyp[o - NX];
+            const cpx<T> mu = msk[o - len], qu = qyp[o - len];
             ta += mu.x * qu.x * idy;
             tb += mu.y * qu.y * idy;
           }
@@ -154,13 +161,13 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   }
   if (store_ex) {
     F::sync_before_reuse();
-    F::template run<-1>(b, a, lds, tw, tid);
+    F::template run<-1>(b, a, lds, tw, tid, len);
 #pragma unroll
     for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
       for (int r = 0; r < QI; ++r) {
         int s, n;
-        if (F::template pos<QI>(tid, q, r, s, n)) ex[(size_t)s * NX + n] = a[q][r];
+        if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) ex[(size_t)s * len + n] = a[q][r];
       }
   }
 }

@@ -22,7 +22,10 @@ PD_MODEL_L1, PD_MODEL_TV = 0, 1
 PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
 KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW = 0, 1, 2, 3, 4
 
-SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512)
+# lengths with a direct FFT plan; any other length 2..MAX_BLUESTEIN runs
+# through the Bluestein (chirp-z) engine
+SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768)
+MAX_BLUESTEIN = 384
 
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",
            "pd_validate", "pd_kernel_norm", "pd_apply_kernel", "pd_now",

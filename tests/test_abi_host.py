@@ -43,11 +43,26 @@ def test_supported_sizes_validate(n):
     assert pd.validate(8, n, 3) > 0
 
 
-@pytest.mark.parametrize("n", [0, 1, 7, 12, 36, 100, 130, 258, 768, 1024])
+@pytest.mark.parametrize("n", [0, 1, -4, 385, 640, 1000, 1024])
 def test_unsupported_sizes_rejected(n):
     with pytest.raises(pd.PdError) as e:
         pd.validate(n, 64, 1)
     assert e.value.status == pd.PD_ERR_SIZE
+
+
+@pytest.mark.parametrize("n", [2, 3, 7, 12, 36, 43, 100, 130, 132, 258, 383, 384])
+def test_any_length_up_to_384_validates(n):
+    # lengths without a direct plan go through the Bluestein engine
+    assert pd.validate(n, 64, 1) > 0
+    assert pd.validate(64, n, 2) > 0
+    assert pd.validate(n, n, 3) > 0
+
+
+def test_bluestein_axis_tables_are_counted_in_the_state():
+    # a 258 axis carries [768 twiddles][258 chirp][768][768] complex table entries
+    small = pd.validate(256, 256, 1)
+    big = pd.validate(256, 258, 1)
+    assert big > small
 
 
 def test_step_condition_matches_oracle_reading():
