@@ -50,6 +50,12 @@ Readings of the paper used here (it is silent or ambiguous on these points):
 The transform is a dense DFT matrix applied along each axis: no FFT
 factorisation, no pairing of slices, and the dual stays in the image domain
 (four transforms per iteration), on purpose different from the GPU path.
+
+3-D kernel (kind="dipole3d"; the "all three dimensions" of Sec. II-A): the
+same iteration with A = F3^-1 diag(D3) F3 over the whole volume,
+D3(k) = 1/3 - (k . b)^2 / |k|^2 on the (kz, ky, kx) grid (kz with voxel size
+voxel_z), D3(0) = 0, averaged between k and -k like the 2-D kernel.  It couples
+the slices; the 2-D kernel is its kz = 0 plane.
 """
 
 import numpy as np
@@ -57,6 +63,7 @@ import numpy as np
 __all__ = [
     "kgrid", "dipole_kernel", "kernel_norm", "check_steps",
     "dft_matrix", "dft2", "idft2", "apply_A", "forward",
+    "dipole_kernel3", "dft3", "idft3", "apply_A3",
     "prox_l1", "prox_dual", "duality_gap", "solve",
 ]
 
@@ -116,6 +123,33 @@ def dipole_kernel(nx, ny, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kind="dipole"):
     return D
 
 
+def dipole_kernel3(nx, ny, nz, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), voxel_z=1.0):
+    """3-D dipole kernel on the (nz, ny, nx) frequency grid:
+    D = 1/3 - (k . b)^2 / |k|^2, D(0) = 0, symmetrised between k and -k."""
+    nx, ny, nz = int(nx), int(ny), int(nz)
+    b = _unit_b0(b0)
+    kx = kgrid(nx, voxel[0])
+    ky = kgrid(ny, voxel[1])
+    kz = kgrid(nz, voxel_z)
+
+    def formula(fx, fy, fz):
+        k2 = fx * fx + fy * fy + fz * fz
+        if k2 == 0.0:
+            return 0.0
+        kb = fx * b[0] + fy * b[1] + fz * b[2]
+        return 1.0 / 3.0 - kb * kb / k2
+
+    D = np.empty((nz, ny, nx), dtype=np.float64)
+    for l in range(nz):
+        lm = (-l) % nz
+        for j in range(ny):
+            jm = (-j) % ny
+            for i in range(nx):
+                im = (-i) % nx
+                D[l, j, i] = 0.5 * (formula(kx[i], ky[j], kz[l]) + formula(kx[im], ky[jm], kz[lm]))
+    return D
+
+
 def kernel_norm(D):
     """||A||_2 = max |D| (A is normal with eigenvalues D)."""
     return float(np.max(np.abs(D)))
@@ -162,6 +196,34 @@ def idft2(X):
     return np.matmul(np.matmul(Wy, X.astype(np.complex128)), Wx.T) / float(nx * ny)
 
 
+def dft3(x):
+    """Unnormalised forward 3-D DFT of the last three axes (nz, ny, nx)."""
+    x = np.asarray(x).astype(np.complex128)
+    nz = x.shape[-3]
+    X = dft2(x)
+    Wz = dft_matrix(nz)
+    return np.einsum("kz,...zyx->...kyx", Wz, X)
+
+
+def idft3(X):
+    """Inverse 3-D DFT of the last three axes, with the 1/(nx ny nz) factor."""
+    X = np.asarray(X).astype(np.complex128)
+    nz = X.shape[-3]
+    x = idft2(X)
+    Wz = dft_matrix(nz, inverse=True)
+    return np.einsum("kz,...zyx->...kyx", Wz, x) / float(nz)
+
+
+def apply_A3(x, D3):
+    """A x = Re F3^-1 (D3 . F3 x) over the whole [nz, ny, nx] volume."""
+    x = np.asarray(x, dtype=np.float64)
+    z = idft3(D3 * dft3(x))
+    scale = max(float(np.max(np.abs(x))) if x.size else 0.0, 1e-300)
+    if float(np.max(np.abs(z.imag))) > 1e-10 * scale:
+        raise AssertionError("A x has a non-negligible imaginary part")
+    return z.real
+
+
 def apply_A(x, D):
     """A x = Re F^-1 (D . F x), slice by slice over leading axes."""
     x = np.asarray(x, dtype=np.float64)
@@ -172,11 +234,24 @@ def apply_A(x, D):
     return z.real
 
 
-def forward(chi, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kind="dipole"):
+def _operator(shape, b0, voxel, kind, voxel_z):
+    """(D, A) for a [nz, ny, nx] stack: the slice-wise 2-D kernel, or the
+    3-D kernel over the whole volume (kind="dipole3d")."""
+    nz, ny, nx = shape
+    if kind == "dipole3d":
+        D = dipole_kernel3(nx, ny, nz, b0, voxel, voxel_z)
+        return D, (lambda x: apply_A3(x, D))
+    D = dipole_kernel(nx, ny, b0, voxel, kind)
+    return D, (lambda x: apply_A(x, D))
+
+
+def forward(chi, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kind="dipole", voxel_z=1.0):
     """Field map produced by a susceptibility stack chi[nz, ny, nx]: A chi."""
     chi = np.asarray(chi, dtype=np.float64)
-    D = dipole_kernel(chi.shape[-1], chi.shape[-2], b0, voxel, kind)
-    return apply_A(chi, D)
+    if chi.ndim == 2:
+        chi = chi[None]
+    _, A = _operator(chi.shape, b0, voxel, kind, voxel_z)
+    return A(chi)
 
 
 # ---------------------------------------------------------------------------
@@ -199,9 +274,10 @@ def prox_dual(w, delta, sigma):
 # Duality gap
 # ---------------------------------------------------------------------------
 
-def duality_gap(chi, y, Ay, delta, D, lam):
-    """(P, Dual, relgap) for the whole stack at the pair (chi, y); Ay = A y."""
-    r = apply_A(chi, D) - delta
+def duality_gap(chi, y, Ay, delta, D, lam, A=None):
+    """(P, Dual, relgap) for the whole stack at the pair (chi, y); Ay = A y.
+    A is the operator (default: the slice-wise A with kernel grid D)."""
+    r = (A(chi) if A is not None else apply_A(chi, D)) - delta
     P = 0.5 * float(np.sum(r * r)) + lam * float(np.sum(np.abs(chi)))
     m = float(np.max(np.abs(Ay))) if Ay.size else 0.0
     s = 1.0 if m == 0.0 else min(1.0, lam / m)
@@ -216,7 +292,7 @@ def duality_gap(chi, y, Ay, delta, D, lam):
 
 def solve(delta, lam, tau=1.4, sigma=1.4, theta=1.0, max_iter=200,
           gap_tol=0.0, check_every=10, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0),
-          kind="dipole", history=None):
+          kind="dipole", history=None, voxel_z=1.0):
     """Primal-dual iteration of the paper's pseudocode on a stack delta[nz, ny, nx].
 
     Returns (chi, info) with info = {iterations, primal, dual, rel_gap, status}.
@@ -230,7 +306,7 @@ def solve(delta, lam, tau=1.4, sigma=1.4, theta=1.0, max_iter=200,
     if delta.ndim != 3:
         raise ValueError("delta must be [nz, ny, nx]")
     nz, ny, nx = delta.shape
-    D = dipole_kernel(nx, ny, b0, voxel, kind)
+    D, A = _operator(delta.shape, b0, voxel, kind, voxel_z)
     check_steps(tau, sigma, theta, D)
     if max_iter < 0:
         raise ValueError("max_iter must be >= 0")
@@ -247,14 +323,14 @@ def solve(delta, lam, tau=1.4, sigma=1.4, theta=1.0, max_iter=200,
     P = Dual = relgap = float("nan")
     status = "ok"
     while n < max_iter:
-        y = prox_dual(y + sigma * apply_A(chibar, D), delta, sigma)
-        Ay = apply_A(y, D)
+        y = prox_dual(y + sigma * A(chibar), delta, sigma)
+        Ay = A(y)
         chi_new = prox_l1(chi - tau * Ay, tau * lam)
         chibar = chi_new + theta * (chi_new - chi)
         chi = chi_new
         n += 1
         if gap_tol > 0 and (n % check_every == 0 or n == max_iter):
-            P, Dual, relgap = duality_gap(chi, y, Ay, delta, D, lam)
+            P, Dual, relgap = duality_gap(chi, y, Ay, delta, D, lam, A)
             if history is not None:
                 history.append((n, P, Dual, relgap))
             if not (np.isfinite(P) and np.isfinite(Dual)):
@@ -263,7 +339,7 @@ def solve(delta, lam, tau=1.4, sigma=1.4, theta=1.0, max_iter=200,
             if relgap <= gap_tol:
                 break
     if gap_tol <= 0 or n == 0:
-        P, Dual, relgap = duality_gap(chi, y, Ay, delta, D, lam)
+        P, Dual, relgap = duality_gap(chi, y, Ay, delta, D, lam, A)
         if not (np.isfinite(P) and np.isfinite(Dual)):
             status = "nonfinite"
     return chi, {"iterations": n, "primal": P, "dual": Dual,

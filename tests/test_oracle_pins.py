@@ -431,3 +431,113 @@ def test_planted_kernel_without_origin_zero_is_caught(monkeypatch):
     _plant(monkeypatch, "dipole_kernel", bad)
     with pytest.raises(AssertionError):
         test_dipole_range_origin_and_evenness(16)
+
+
+# ---------------------------------------------------------------------------
+# 3-D kernel (whole-volume operator)
+# ---------------------------------------------------------------------------
+
+def load_kernel3_fixture(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        lines = [l.strip() for l in f if l.strip() and not l.startswith("#")]
+    hdr = lines[0].split()
+    nx, ny, nz = int(hdr[0]), int(hdr[1]), int(hdr[2])
+    b = tuple(float(v) for v in hdr[3:6])
+    vox = (float(hdr[6]), float(hdr[7]))
+    dz = float(hdr[8])
+    vals = [[float(Fraction(t)) for t in l.split()] for l in lines[1:]]
+    D = np.array(vals).reshape(nz, ny, nx)
+    return nx, ny, nz, b, vox, dz, D
+
+
+@pytest.mark.parametrize("name", ["dipole3d_2x2x2_b0z.txt", "dipole3d_2x2x2_b0xy.txt",
+                                  "dipole3d_3x1x2_b0z_dz2.txt"])
+def test_dipole3d_kernel_hand_derived(name):
+    nx, ny, nz, b, vox, dz, D = load_kernel3_fixture(name)
+    np.testing.assert_allclose(O.dipole_kernel3(nx, ny, nz, b, vox, dz), D, atol=1e-15)
+
+
+@pytest.mark.parametrize("b0", [(0, 1, 0), (0.3, 0.5, 0.8), (1, 0, 1)])
+def test_dipole3d_kz0_plane_is_the_2d_kernel(b0):
+    D3 = O.dipole_kernel3(12, 8, 6, b0, (0.8, 1.1), 2.0)
+    np.testing.assert_allclose(D3[0], O.dipole_kernel(12, 8, b0, (0.8, 1.1)), atol=1e-15)
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 7), (8, 8, 8)])
+def test_dipole3d_range_origin_and_evenness(shape):
+    nz, ny, nx = shape
+    D = O.dipole_kernel3(nx, ny, nz, (0.2, 0.7, 0.4), (1.0, 0.9), 1.5)
+    assert D[0, 0, 0] == 0.0
+    assert D.min() >= -2.0 / 3.0 - 1e-15 and D.max() <= 1.0 / 3.0 + 1e-15
+    neg = D[(-np.arange(nz)) % nz][:, (-np.arange(ny)) % ny][:, :, (-np.arange(nx)) % nx]
+    np.testing.assert_allclose(D, neg, atol=1e-15)
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 7)])
+def test_dft3_round_trip_parseval_and_library(shape):
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    X = O.dft3(x)
+    np.testing.assert_allclose(X, np.fft.fftn(x), atol=1e-11)
+    np.testing.assert_allclose(O.idft3(X), x, atol=1e-13)
+    n = np.prod(shape)
+    np.testing.assert_allclose(np.sum(np.abs(X) ** 2) / n, np.sum(np.abs(x) ** 2), rtol=1e-13)
+
+
+def dense_A3_from_cosines(D):
+    """Dense A on an nz x ny x nx volume from explicit cosine sums."""
+    nz, ny, nx = D.shape
+    n = nx * ny * nz
+    idx = np.arange(n)
+    zs, rem = np.divmod(idx, nx * ny)
+    ys, xs = np.divmod(rem, nx)
+    A = np.zeros((n, n))
+    for kz in range(nz):
+        for ky in range(ny):
+            for kx in range(nx):
+                if D[kz, ky, kx] == 0.0:
+                    continue
+                ph = 2.0 * np.pi * (kx * xs / nx + ky * ys / ny + kz * zs / nz)
+                c, s = np.cos(ph), np.sin(ph)
+                A += D[kz, ky, kx] * (np.outer(c, c) + np.outer(s, s))
+    return A / n
+
+
+def test_dense_3d_operator_matches_apply_A3():
+    D = O.dipole_kernel3(4, 3, 2, (0.3, 0.5, 0.8), (1.0, 0.8), 1.6)
+    A = dense_A3_from_cosines(D)
+    np.testing.assert_allclose(A, A.T, atol=1e-14)
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=(2, 3, 4))
+    np.testing.assert_allclose(O.apply_A3(x, D).ravel(), A @ x.ravel(), atol=1e-13)
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(A)), np.sort(D.ravel()), atol=1e-12)
+
+
+def test_3d_operator_on_z_constant_volume_is_the_slice_operator():
+    # a volume constant along z has only kz = 0 content, where D3 = D2
+    rng = np.random.default_rng(10)
+    sl = rng.normal(size=(6, 8))
+    x = np.broadcast_to(sl, (4, 6, 8)).copy()
+    a3 = O.forward(x, b0=(0.3, 0.5, 0.8), kind="dipole3d", voxel_z=2.0)
+    a2 = O.forward(x, b0=(0.3, 0.5, 0.8))
+    np.testing.assert_allclose(a3, a2, atol=1e-12)
+
+
+def test_3d_pd_equals_dense_matrix_pd():
+    D = O.dipole_kernel3(4, 3, 2, (0.3, 0.5, 0.8), (1.0, 0.8), 1.6)
+    A = dense_A3_from_cosines(D)
+    rng = np.random.default_rng(11)
+    d = rng.normal(size=(2, 3, 4)) * 2
+    lam, tau, sigma, theta = 0.05, 1.4, 1.4, 1.0
+    ref = dense_pd(A, d.ravel(), lam, tau, sigma, theta, 40)
+    chi, _ = O.solve(d, lam, tau, sigma, theta, 40, b0=(0.3, 0.5, 0.8), voxel=(1.0, 0.8), kind="dipole3d",
+                     voxel_z=1.6)
+    np.testing.assert_allclose(chi.ravel(), ref, atol=1e-11)
+
+
+def test_planted_ignored_slice_thickness_is_caught(monkeypatch):
+    good = O.pd_oracle.dipole_kernel3
+    _plant(monkeypatch, "dipole_kernel3",
+           lambda nx, ny, nz, b0=(0, 1, 0), voxel=(1, 1), voxel_z=1.0: good(nx, ny, nz, b0, voxel, 1.0))
+    with pytest.raises(AssertionError):
+        test_dipole3d_kernel_hand_derived("dipole3d_3x1x2_b0z_dz2.txt")
