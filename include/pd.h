@@ -53,7 +53,17 @@ enum {
 };
 
 enum { PD_FP32 = 0, PD_FP64 = 1 };                      /* pd_config.precision */
-enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1 };  /* pd_request.kernel   */
+/* pd_request.kernel:
+ *   PD_KERNEL_DIPOLE     the 2-D kernel of each slice (slices independent);
+ *   PD_KERNEL_IDENTITY   D = 1 (A = I; closed-form checks);
+ *   PD_KERNEL_DIPOLE_3D  the 3-D kernel over the whole volume,
+ *                        D(k) = 1/3 - (k.b)^2/|k|^2 with k = (kx, ky, kz),
+ *                        kz on the nz grid with slice thickness voxel_z
+ *                        (the paper's "all three dimensions"; Sec. II-A).
+ *                        It couples the slices: every iteration transforms
+ *                        along z too.  L1 model only; nz >= 2 and a
+ *                        supported length like nx and ny.                    */
+enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1, PD_KERNEL_DIPOLE_3D = 2 };
 /* pd_request.model:
  *   PD_MODEL_L1  min 1/2||A chi - delta||^2 + lambda ||chi||_1 (see the top),
  *                with the duality-gap stop rule available;
@@ -111,7 +121,7 @@ typedef struct {
                           smallest direct length >= 2n - 1                      */
   double b0[3];        /* B0 direction in voxel axes (x, y, z); any non-zero scale */
   double voxel[2];     /* in-plane voxel size (dx, dy), any positive unit          */
-  int kernel;          /* PD_KERNEL_DIPOLE, or PD_KERNEL_IDENTITY (D = 1)          */
+  int kernel;          /* PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY or PD_KERNEL_DIPOLE_3D */
   double lambda;       /* weight of the L1 term (> 0)                              */
   double tau, sigma;   /* primal and dual step sizes (PD pseudocode, step 1)       */
   double theta;        /* over-relaxation in [0, 1]                                */
@@ -126,6 +136,8 @@ typedef struct {
   const void* weight;  /* TV model: W [nz][ny][nx] (like delta: valid, unchanged
                           until completion); non-NULL for PD_MODEL_TV           */
   const void* mask;    /* TV model: M [nz][ny][nx], same rules                     */
+  double voxel_z;      /* slice thickness (same unit as voxel), > 0; read only
+                          for PD_KERNEL_DIPOLE_3D                                   */
 } pd_request;
 /* TV model specifics: gap_tol must be 0 and lambda > 0 (PD_ERR_ARG otherwise);
  * check_every is ignored.  Its step condition, tau*sigma*L2 < 1 with

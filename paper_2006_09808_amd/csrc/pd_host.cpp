@@ -87,6 +87,31 @@ void dipole_grid(int nx, int ny, const double b[3], const double vox[2], int ker
   }
 }
 
+// 3-D kernel on the [nz][ny][nx] grid (kz with slice thickness dz), averaged
+// between k and -k: f(index, value) for every grid point in index order (the
+// grid is generated, not stored: it can hold 10^8 points)
+template <typename Fn>
+void dipole_grid3(int nx, int ny, int nz, const double b[3], const double vox[2], double dz, Fn&& out) {
+  double bu[3];
+  unit_b0(b, bu);
+  auto f = [&](double kx, double ky, double kz) {
+    double k2 = kx * kx + ky * ky + kz * kz;
+    if (k2 == 0.0) return 0.0;
+    double kb = kx * bu[0] + ky * bu[1] + kz * bu[2];
+    return 1.0 / 3.0 - kb * kb / k2;
+  };
+  for (int l = 0; l < nz; ++l) {
+    double kz = kfreq(l, nz, dz), kzm = kfreq((nz - l) % nz, nz, dz);
+    for (int j = 0; j < ny; ++j) {
+      double ky = kfreq(j, ny, vox[1]), kym = kfreq((ny - j) % ny, ny, vox[1]);
+      for (int i = 0; i < nx; ++i) {
+        double kx = kfreq(i, nx, vox[0]), kxm = kfreq((nx - i) % nx, nx, vox[0]);
+        out(((size_t)l * ny + j) * nx + i, 0.5 * (f(kx, ky, kz) + f(kxm, kym, kzm)));
+      }
+    }
+  }
+}
+
 double grid_norm(const std::vector<double>& D) {
   double m = 0.0;
   for (double d : D) m = std::max(m, std::fabs(d));
@@ -211,12 +236,20 @@ struct Layout {
   size_t total;
   bool separate_ex2;
   bool tv;
+  bool unpacked;                    // 3-D kernel: one slice per plane, P = nz
+  int zgroups, ext_z;               // 3-D kernel: z-transform workgroups, kernel variant
 };
 
 Layout layout_of(const pd_request& r, int precision) {
   Layout L{};
   size_t esz = precision == PD_FP64 ? 16 : 8;
-  L.P = (r.nz + 1) / 2;
+  L.unpacked = r.kernel == PD_KERNEL_DIPOLE_3D;
+  L.P = L.unpacked ? r.nz : (r.nz + 1) / 2;
+  if (L.unpacked) {
+    // z transforms: strips of 8 of the nx ny columns of the [nz][ny nx] view
+    L.zgroups = ceil_div(r.nx * r.ny, 8);
+    L.ext_z = axis_ext(r.nz, r.nx * r.ny, 8);
+  }
   L.rows = rows_per_wg(r.nx, r.ny, precision);
   L.cols = cols_per_wg(r.nx, r.ny, precision);
   L.row_groups = ceil_div(r.ny, L.rows);
@@ -252,25 +285,44 @@ Layout layout_of(const pd_request& r, int precision) {
   // any resident team (at most 32 workgroups per pair)
   size_t pg = (size_t)std::max(std::max(ceil_div(r.ny, 8), ceil_div(r.nx, 8)), 32);
   L.off_prow = o; o += align_up((size_t)L.P * pg * 2 * sizeof(double));
-  L.off_pcol = o; o += align_up((size_t)L.P * pg * 3 * sizeof(double));
+  const size_t ncol = std::max((size_t)L.P * pg, (size_t)L.zgroups);
+  L.off_pcol = o; o += align_up(ncol * 3 * sizeof(double));
   L.total = o;
   return L;
 }
 
-size_t table_bytes(int nx, int ny, int precision) {
+// D grid ([nz3][ny][nx], nz3 = 1 for the 2-D kernels) and the twiddle tables
+// of x, y (and z for the 3-D kernel, nz3 > 1)
+size_t table_bytes(int nx, int ny, int nz3, int precision) {
   size_t t = precision == PD_FP64 ? 8 : 4;
-  return align_up((size_t)nx * ny * t) + align_up(axis_tw_entries(nx) * 2 * t) + align_up(axis_tw_entries(ny) * 2 * t);
+  size_t b = align_up((size_t)nx * ny * std::max(nz3, 1) * t) + align_up(axis_tw_entries(nx) * 2 * t) +
+             align_up(axis_tw_entries(ny) * 2 * t);
+  if (nz3 > 1) b += align_up(axis_tw_entries(nz3) * 2 * t);
+  return b;
+}
+inline int nz3_of(const pd_request& r) { return r.kernel == PD_KERNEL_DIPOLE_3D ? r.nz : 0; }
+
+// kernel, B0, voxel and (3-D kernel) slice thickness and z length
+pd_status kernel_args(const pd_request* r) {
+  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY && r->kernel != PD_KERNEL_DIPOLE_3D)
+    return PD_ERR_ARG;
+  double bu[3];
+  if (r->kernel != PD_KERNEL_IDENTITY && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
+  if (!isfin(r->voxel[0]) || !isfin(r->voxel[1]) || r->voxel[0] <= 0 || r->voxel[1] <= 0) return PD_ERR_ARG;
+  if (r->kernel == PD_KERNEL_DIPOLE_3D) {
+    if (!isfin(r->voxel_z) || r->voxel_z <= 0) return PD_ERR_ARG;
+    if (!axis_ok(r->nz)) return PD_ERR_SIZE;
+  }
+  return PD_OK;
 }
 
 pd_status validate(const pd_request* r, int precision, double* norm_out) {
   if (!r) return PD_ERR_ARG;
   if (precision != PD_FP32 && precision != PD_FP64) return PD_ERR_ARG;
   if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
-  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
-  double bu[3];
-  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
-  if (!isfin(r->voxel[0]) || !isfin(r->voxel[1]) || r->voxel[0] <= 0 || r->voxel[1] <= 0)
-    return PD_ERR_ARG;
+  pd_status ks = kernel_args(r);
+  if (ks != PD_OK) return ks;
+  if (r->kernel == PD_KERNEL_DIPOLE_3D && r->model != PD_MODEL_L1) return PD_ERR_ARG;
   if (!isfin(r->lambda) || r->lambda < 0) return PD_ERR_ARG;
   if (r->max_iter < 0) return PD_ERR_ARG;
   if (!isfin(r->gap_tol) || r->gap_tol < 0) return PD_ERR_ARG;
@@ -284,9 +336,15 @@ pd_status validate(const pd_request* r, int precision, double* norm_out) {
   }
   if (!isfin(r->tau) || !isfin(r->sigma) || r->tau <= 0 || r->sigma <= 0) return PD_ERR_STEP;
   if (!isfin(r->theta) || r->theta < 0 || r->theta > 1) return PD_ERR_STEP;
-  std::vector<double> D;
-  dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
-  double L = grid_norm(D);
+  double L = 0.0;
+  if (r->kernel == PD_KERNEL_DIPOLE_3D) {
+    dipole_grid3(r->nx, r->ny, r->nz, r->b0, r->voxel, r->voxel_z,
+                 [&](size_t, double d) { L = std::max(L, std::fabs(d)); });
+  } else {
+    std::vector<double> D;
+    dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
+    L = grid_norm(D);
+  }
   // the TV model's condition also needs max|W| and max|M|: tested on the
   // device at admission
   if (r->model == PD_MODEL_L1 && !(r->tau * r->sigma * L * L < 1.0)) return PD_ERR_STEP;
@@ -350,11 +408,14 @@ class Arena {
 // per kernel shape: D grid and the twiddles of both axes, in the arena
 struct TableKey {
   int nx, ny, kernel;
-  double b[3], vox[2];
+  int nz3;                          // 3-D kernel: nz; else 0
+  double b[3], vox[2], vz;
   bool operator<(const TableKey& o) const {
     if (nx != o.nx) return nx < o.nx;
     if (ny != o.ny) return ny < o.ny;
     if (kernel != o.kernel) return kernel < o.kernel;
+    if (nz3 != o.nz3) return nz3 < o.nz3;
+    if (vz != o.vz) return vz < o.vz;
     for (int i = 0; i < 3; ++i)
       if (b[i] != o.b[i]) return b[i] < o.b[i];
     for (int i = 0; i < 2; ++i)
@@ -366,7 +427,7 @@ struct Table {
   size_t off = 0, bytes = 0;
   int refs = 0;
   bool uploaded = false;
-  void *d = nullptr, *twx = nullptr, *twy = nullptr;
+  void *d = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
 };
 
 struct Job {
@@ -386,10 +447,12 @@ struct Job {
 
 struct GroupKey {
   int nx, ny, model;
+  int nz3;                          // 3-D kernel: nz (volumes batch only with equal nz); else 0
   bool operator<(const GroupKey& o) const {
     if (nx != o.nx) return nx < o.nx;
     if (ny != o.ny) return ny < o.ny;
-    return model < o.model;
+    if (model != o.model) return model < o.model;
+    return nz3 < o.nz3;
   }
 };
 
@@ -420,7 +483,8 @@ struct pd_ctx {
   // control arrays: device copies carved from the arena, pinned host mirrors.
   // Entry nslots of vols/ctl/ranges is reserved for pd_apply_kernel.
   size_t ctl_off = 0, ctl_bytes = 0;
-  Vol* d_vols = nullptr;       // nslots + 1
+  Vol* d_vols = nullptr;       // 2 (nslots + 1): plane views, then the 3-D kernel's z views from zoff
+  int zoff = 0;
   Ctl* d_ctl = nullptr;        // nslots + 1
   int* d_slots = nullptr;      // nslots
   Range* d_ranges = nullptr;   // range_cap
@@ -454,7 +518,7 @@ struct pd_ctx {
   // kernel timing
   bool time_kernels = false;
   std::mutex tmu;
-  static constexpr int kKinds = 5;        // column, row, resident, TV column, TV row
+  static constexpr int kKinds = 6;        // column, row, resident, TV column, TV row, 3-D z transform
   int64_t t_launches[kKinds] = {};
   double t_ms[kKinds] = {};
   double t_points[kKinds] = {};           // iterations x slice-pair points processed
@@ -478,13 +542,14 @@ Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
     return &it->second;
   }
   Table t;
-  t.bytes = table_bytes(k.nx, k.ny, c->precision);
+  t.bytes = table_bytes(k.nx, k.ny, k.nz3, c->precision);
   if (!c->arena.alloc(t.bytes, &t.off)) return nullptr;
   size_t tsz = c->precision == PD_FP64 ? 8 : 4;
   char* p = c->arena.ptr(t.off);
   t.d = p;
-  t.twx = p + align_up((size_t)k.nx * k.ny * tsz);
+  t.twx = p + align_up((size_t)k.nx * k.ny * std::max(k.nz3, 1) * tsz);
   t.twy = (char*)t.twx + align_up(axis_tw_entries(k.nx) * 2 * tsz);
+  t.twz = k.nz3 > 1 ? (char*)t.twy + align_up(axis_tw_entries(k.ny) * 2 * tsz) : nullptr;
   t.refs = 1;
   t.uploaded = false;
   *fresh = true;
@@ -502,15 +567,22 @@ void release_table(pd_ctx* c, const TableKey& k) {
 
 template <typename T>
 hipError_t upload_table(pd_ctx* c, const TableKey& k, const Table& t) {
-  std::vector<double> D, re, im;
-  dipole_grid(k.nx, k.ny, k.b, k.vox, k.kernel, D);
-  std::vector<T> hd(D.size());
-  for (size_t i = 0; i < D.size(); ++i) hd[i] = (T)D[i];
+  std::vector<double> re, im;
+  std::vector<T> hd;
+  if (k.nz3 > 1) {
+    hd.resize((size_t)k.nx * k.ny * k.nz3);
+    dipole_grid3(k.nx, k.ny, k.nz3, k.b, k.vox, k.vz, [&](size_t i, double d) { hd[i] = (T)d; });
+  } else {
+    std::vector<double> D;
+    dipole_grid(k.nx, k.ny, k.b, k.vox, k.kernel, D);
+    hd.resize(D.size());
+    for (size_t i = 0; i < D.size(); ++i) hd[i] = (T)D[i];
+  }
   hipError_t e = hipMemcpyAsync(t.d, hd.data(), hd.size() * sizeof(T), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
-  std::vector<std::vector<T>> tws(2);
-  for (int axis = 0; axis < 2; ++axis) {
-    int n = axis == 0 ? k.nx : k.ny;
+  std::vector<std::vector<T>> tws(3);
+  for (int axis = 0; axis < (k.nz3 > 1 ? 3 : 2); ++axis) {
+    int n = axis == 0 ? k.nx : axis == 1 ? k.ny : k.nz3;
     std::vector<T>& tw = tws[axis];
     if (!axis_blue(n)) {
       twiddles(n, re, im);
@@ -525,8 +597,8 @@ hipError_t upload_table(pd_ctx* c, const TableKey& k, const Table& t) {
       tw.resize(all.size());
       for (size_t m = 0; m < all.size(); ++m) tw[m] = (T)all[m];
     }
-    e = hipMemcpyAsync(axis == 0 ? t.twx : t.twy, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice,
-                       c->stream);
+    e = hipMemcpyAsync(axis == 0 ? t.twx : axis == 1 ? t.twy : t.twz, tw.data(), tw.size() * sizeof(T),
+                       hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return e;
   }
   // the host vectors die on return: wait for the copies
@@ -538,12 +610,14 @@ TableKey key_of(const pd_request& r) {
   k.nx = r.nx;
   k.ny = r.ny;
   k.kernel = r.kernel;
-  if (r.kernel == PD_KERNEL_DIPOLE) {
+  k.nz3 = nz3_of(r);
+  k.vz = k.nz3 ? r.voxel_z : 0.0;
+  if (r.kernel != PD_KERNEL_IDENTITY) {
     unit_b0(r.b0, k.b);
   } else {
     k.b[0] = k.b[1] = k.b[2] = 0.0;
   }
-  if (r.kernel == PD_KERNEL_DIPOLE) {
+  if (r.kernel != PD_KERNEL_IDENTITY) {
     k.vox[0] = r.voxel[0];
     k.vox[1] = r.voxel[1];
   } else {
@@ -600,6 +674,26 @@ void fill_vol(pd_ctx* c, const Job& j, Vol& V) {
   V.inv_dx = 1.0 / j.req.voxel[0];
   V.inv_dy = 1.0 / j.req.voxel[1];
   V.knorm = j.knorm;
+  V.unpacked = j.L.unpacked ? 1 : 0;
+  if (j.L.unpacked) V.half_last = 0;
+  V.gap_norm = 1.0 / ((double)j.req.nx * (double)j.req.ny * (j.L.unpacked ? (double)j.req.nz : 1.0));
+  V.col_parts = j.L.unpacked ? j.L.zgroups : V.P * V.col_groups;
+}
+
+// The 3-D kernel's z view of a volume: the [nz][ny][nx] planes read as one
+// slice of nz rows by nx ny columns, so the column kernel transforms along z
+// (D table [nz][ny nx], twiddles of z).  Same buffers and controls as V.
+void fill_zvol(const Job& j, const Vol& V, Vol& Z) {
+  Z = V;
+  Z.nx = j.req.nx * j.req.ny;
+  Z.ny = j.req.nz;
+  Z.P = 1;
+  Z.half_last = 0;
+  Z.unpacked = 0;
+  Z.twx = nullptr;
+  Z.twy = j.tab.twz;
+  Z.row_groups = 0;
+  Z.col_groups = j.L.zgroups;
 }
 
 // Reserve arena + slot for a queued job; caller holds c->mu.  Returns false
@@ -648,6 +742,13 @@ hipError_t setup_job(pd_ctx* c, Job& j) {
   fill_vol(c, j, V);
   hipError_t e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
+  if (j.L.unpacked) {
+    Vol& Z = c->h_vols[c->zoff + j.slot];
+    fill_zvol(j, V, Z);
+    if ((e = hipMemcpyAsync(c->d_vols + c->zoff + j.slot, &Z, sizeof(Vol), hipMemcpyHostToDevice, c->stream)) !=
+        hipSuccess)
+      return e;
+  }
   char* base = c->arena.ptr(j.off);
   if ((e = launch_zero(base, j.L.total, c->stream)) != hipSuccess) return e;
   if ((e = launch_zero(c->d_ctl + j.slot, sizeof(Ctl), c->stream)) != hipSuccess) return e;
@@ -675,6 +776,17 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
     e = launch_row(axis_phys(j->req.nx), ROW_FWD_PLANAR, j->L.rows, P * j->L.row_groups, j->L.row_groups, c->d_vols,
                    rg, 1, c->d_ctl, 0, c->precision, j->L.ext_row, c->stream);
     if (e != hipSuccess) return e;
+    if (j->L.unpacked) {   // 3-D kernel: F_y in place, then F_z of the z view -> dhat
+      e = launch_col(axis_phys(j->req.ny), COL_FWD, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols, rg,
+                     1, c->d_ctl, -1, c->precision, j->L.ext_col, c->stream);
+      if (e != hipSuccess) return e;
+      e = launch_col(axis_phys(j->req.nz), COL_SETUP, 8, j->L.zgroups, j->L.zgroups, c->d_vols + c->zoff, rg, 1,
+                     c->d_ctl, 0, c->precision, j->L.ext_z, c->stream);
+      if (e != hipSuccess) return e;
+      e = launch_zero(c->arena.ptr(j->off) + j->L.off_ex, j->L.field, c->stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     e = launch_col(axis_phys(j->req.ny), COL_SETUP, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols,
                    rg, 1, c->d_ctl, 0, c->precision, j->L.ext_col, c->stream);
     if (e != hipSuccess) return e;
@@ -709,7 +821,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   int nslot_list = 0;
   bool any_check = false;
   for (auto& j : act) {
-    groups[GroupKey{j->req.nx, j->req.ny, j->req.model}].push_back(j.get());
+    groups[GroupKey{j->req.nx, j->req.ny, j->req.model, nz3_of(j->req)}].push_back(j.get());
     Vol& V = c->h_vols[j->slot];
     fill_vol(c, *j, V);
     if (j->L.tv) {                  // fixed iteration count, no gap checks
@@ -743,6 +855,8 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     bool resident;
     bool tv;                                 // weighted TV model (four launches per iteration)
     int px, py, er, ec;                      // transform lengths and kernel variants (row, column)
+    bool z3;                                 // 3-D kernel: planes plus the z view
+    int pz, ez, zg, z_off, nzr;              // z: transform length, variant, groups per volume, ranges
     int team;
     const ResidentVariant* rv;
     int range_off, nranges, npairs;          // resident: one range table
@@ -760,8 +874,10 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     int nx = g.first.nx, ny = g.first.ny;
     const pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
     const bool tv = g.first.model == PD_MODEL_TV;
+    const bool z3 = g.first.nz3 > 0;
     const ResidentVariant* rv =
-        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv)
+        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv &&
+         !z3)
             ? resident_variant(nx, tn.res_variant) : nullptr;
     int team = rv ? rv->team() : 0;
     int maxt = team ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
@@ -822,6 +938,20 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
         fits &= push_range(j->slot, np * L.cg, 0);
         np += j->L.P;
       }
+      if (z3) {   // one z-view range per volume
+        Job* j0 = g.second.front();
+        L.z3 = true;
+        L.zg = j0->L.zgroups;
+        L.pz = axis_phys(j0->req.nz);
+        L.ez = j0->L.ext_z;
+        L.z_off = (int)k;
+        int nv = 0;
+        for (Job* j : g.second) {
+          fits &= push_range(j->slot, nv * L.zg, 0);
+          ++nv;
+        }
+        L.nzr = nv;
+      }
       launches.push_back(L);
     }
   }
@@ -833,13 +963,18 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
         Vol& V = c->h_vols[c->h_ranges[L.range_off + i].slot];
         V.row_groups = V.col_groups = L.team;
       }
+  for (auto& j : act) {
+    Vol& V = c->h_vols[j->slot];
+    V.col_parts = j->L.unpacked ? j->L.zgroups : V.P * V.col_groups;
+    if (j->L.unpacked) fill_zvol(*j, V, c->h_vols[c->zoff + j->slot]);
+  }
 
   hipError_t e;
   if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, sizeof(Range) * k, hipMemcpyHostToDevice, c->stream)) !=
       hipSuccess)
     return e;
-  if ((e = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * c->nslots, hipMemcpyHostToDevice, c->stream)) !=
-      hipSuccess)
+  if ((e = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipMemcpyHostToDevice,
+                          c->stream)) != hipSuccess)
     return e;
   if ((e = hipMemcpyAsync(c->d_slots, c->h_slots, sizeof(int) * nslot_list, hipMemcpyHostToDevice,
                           c->stream)) != hipSuccess)
@@ -902,6 +1037,30 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
             return launch_row(L.px, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
                               it, c->precision, L.er, c->stream);
           };
+          if (L.z3) {   // 3-D kernel: F_y, (F_z, dual prox, F_z^-1) on the z view, F_y^-1, row kernel
+            const Range* rz = c->d_ranges + L.z_off;
+            auto cfwd = [&] {
+              return launch_col(L.py, COL_FWD, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, c->stream);
+            };
+            auto zk = [&] {
+              return launch_col(L.pz, COL_ITER, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
+                                c->precision, L.ez, c->stream);
+            };
+            auto cinv = [&] {
+              return launch_col(L.py, COL_INV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, c->stream);
+            };
+            r = with_events ? timed(0, pts, cfwd) : cfwd();
+            if (r != hipSuccess) return r;
+            r = with_events ? timed(5, pts, zk) : zk();
+            if (r != hipSuccess) return r;
+            r = with_events ? timed(0, pts, cinv) : cinv();
+            if (r != hipSuccess) return r;
+            r = with_events ? timed(1, pts, row) : row();
+            if (r != hipSuccess) return r;
+            continue;
+          }
           if (L.tv) {
             auto col_tv = [&] {
               return launch_col(L.py, COL_TV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
@@ -932,6 +1091,15 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
         for (auto& L : launches) {
           if (L.resident || L.tv) continue;
           const Range* rcol = c->d_ranges + L.col_off;
+          if (L.z3) {   // F_y of the check buffer in place, then F_z and the partials on the z view
+            r = launch_col(L.py, COL_FWD_CHK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                           K - 1, c->precision, L.ec, c->stream);
+            if (r != hipSuccess) return r;
+            r = launch_col(L.pz, COL_CHECK, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, c->d_ranges + L.z_off,
+                           L.nzr, c->d_ctl, K - 1, c->precision, L.ez, c->stream);
+            if (r != hipSuccess) return r;
+            continue;
+          }
           r = launch_col(L.py, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                          K - 1, c->precision, L.ec, c->stream);
           if (r != hipSuccess) return r;
@@ -951,8 +1119,10 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
                       std::to_string(c->precision);
     for (auto& L : launches) {
       if (L.resident) continue;
-      sig += "|" + std::string(L.tv ? "tv" : "l1") + std::to_string(L.nx) + "," + std::to_string(L.ny) + "," +
-             std::to_string(L.rows) + "," +
+      sig += "|" + std::string(L.tv ? "tv" : "l1") + (L.z3 ? "z" + std::to_string(L.pz) + "," + std::to_string(L.zg) + "," +
+                                                                std::to_string(L.z_off) + "," + std::to_string(L.nzr)
+                                                          : std::string()) +
+             std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
              std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
              std::to_string(L.row_off) + "," + std::to_string(L.col_off);
     }
@@ -1158,19 +1328,25 @@ double pd_now(void) { return now_s(); }
 pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes) {
   pd_status s = validate(r, precision, nullptr);
   if (s != PD_OK) return s;
-  if (state_bytes) *state_bytes = layout_of(*r, precision).total + table_bytes(r->nx, r->ny, precision);
+  if (state_bytes) *state_bytes = layout_of(*r, precision).total + table_bytes(r->nx, r->ny, nz3_of(*r), precision);
   return PD_OK;
 }
 
 pd_status pd_kernel_norm(const pd_request* r, double* norm) {
   if (!r || !norm) return PD_ERR_ARG;
   if (!axis_ok(r->nx) || !axis_ok(r->ny)) return PD_ERR_SIZE;
-  double bu[3];
-  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
-  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
-  std::vector<double> D;
-  dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
-  *norm = grid_norm(D);
+  pd_status ks = kernel_args(r);
+  if (ks != PD_OK) return ks;
+  double L = 0.0;
+  if (r->kernel == PD_KERNEL_DIPOLE_3D) {
+    dipole_grid3(r->nx, r->ny, r->nz, r->b0, r->voxel, r->voxel_z,
+                 [&](size_t, double d) { L = std::max(L, std::fabs(d)); });
+  } else {
+    std::vector<double> D;
+    dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
+    L = grid_norm(D);
+  }
+  *norm = L;
   return PD_OK;
 }
 
@@ -1194,13 +1370,14 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->arena.init((char*)cfg->arena, cfg->arena_bytes);
 
   c->range_cap = 4 * (size_t)c->nslots + 4096;
-  c->ctl_bytes = align_up(sizeof(Vol) * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
+  c->zoff = c->nslots + 1;
+  c->ctl_bytes = align_up(sizeof(Vol) * 2 * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
                  align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * c->range_cap) +
                  align_up(counter_bytes(kMaxTeamSlots)) + align_up(sizeof(int));
   if (!c->arena.alloc(c->ctl_bytes, &c->ctl_off)) return PD_ERR_BUDGET;
   char* p = c->arena.ptr(c->ctl_off);
   c->d_vols = (Vol*)p;
-  p += align_up(sizeof(Vol) * (c->nslots + 1));
+  p += align_up(sizeof(Vol) * 2 * (c->nslots + 1));
   c->d_ctl = (Ctl*)p;
   p += align_up(sizeof(Ctl) * (c->nslots + 1));
   c->d_slots = (int*)p;
@@ -1217,7 +1394,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return PD_ERR_HIP;
     c->own_stream = true;
   }
-  if (hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
+  if (hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_slots, sizeof(int) * c->nslots, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * c->range_cap, hipHostMallocDefault) != hipSuccess ||
@@ -1231,11 +1408,11 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
     return PD_ERR_HIP;
   }
   *c->h_abort = 0;
-  std::memset(c->h_vols, 0, sizeof(Vol) * (c->nslots + 1));
+  std::memset(c->h_vols, 0, sizeof(Vol) * 2 * (c->nslots + 1));
   std::memset(c->h_ctl, 0, sizeof(Ctl) * (c->nslots + 1));
   for (int s = c->nslots - 1; s >= 0; --s) c->free_slots.push_back(s);
   // all descriptors start idle (iters = 0)
-  if (hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * (c->nslots + 1), hipMemcpyHostToDevice, c->stream) !=
+  if (hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipMemcpyHostToDevice, c->stream) !=
           hipSuccess ||
       launch_zero(c->d_ctl, sizeof(Ctl) * (c->nslots + 1), c->stream) != hipSuccess ||
       launch_zero(c->d_abort, align_up(sizeof(int)), c->stream) != hipSuccess ||
@@ -1268,7 +1445,7 @@ pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* ticket
     j->L = layout_of(r[i], c->precision);
     j->key = key_of(r[i]);
     // the request and its table must fit in an otherwise empty arena
-    size_t need = j->L.total + table_bytes(r[i].nx, r[i].ny, c->precision);
+    size_t need = j->L.total + table_bytes(r[i].nx, r[i].ny, nz3_of(r[i]), c->precision);
     if (need > avail) return PD_ERR_BUDGET;
     js.push_back(j);
   }
@@ -1335,10 +1512,8 @@ pd_status pd_destroy(pd_ctx* c) {
 pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
   if (!c || !r) return PD_ERR_ARG;
   if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
-  if (r->kernel != PD_KERNEL_DIPOLE && r->kernel != PD_KERNEL_IDENTITY) return PD_ERR_ARG;
-  double bu[3];
-  if (r->kernel == PD_KERNEL_DIPOLE && !unit_b0(r->b0, bu)) return PD_ERR_ARG;
-  if (!isfin(r->voxel[0]) || !isfin(r->voxel[1]) || r->voxel[0] <= 0 || r->voxel[1] <= 0) return PD_ERR_ARG;
+  pd_status ks = kernel_args(r);
+  if (ks != PD_OK) return ks;
   if (!r->delta || !r->chi || r->delta == r->chi) return PD_ERR_ARG;
 
   // Only the exchange buffer is used: every state pointer of the descriptor
@@ -1382,13 +1557,29 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && j.L.unpacked) {
+      Vol& Z = c->h_vols[c->zoff + j.slot];
+      fill_zvol(j, V, Z);
+      e = hipMemcpyAsync(c->d_vols + c->zoff + j.slot, &Z, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+    }
     const int P = j.L.P;
     if (e == hipSuccess)
       e = launch_row(axis_phys(r->nx), ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
                      1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
-    if (e == hipSuccess)
+    if (j.L.unpacked) {   // 3-D kernel: F_y, then (F_z, D, F_z^-1) on the z view, then F_y^-1
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->ny), COL_FWD, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->nz), COL_APPLY, 8, j.L.zgroups, j.L.zgroups, c->d_vols + c->zoff, dr, 1,
+                       c->d_ctl, 0, c->precision, j.L.ext_z, c->stream);
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->ny), COL_INV, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
+    } else if (e == hipSuccess) {
       e = launch_col(axis_phys(r->ny), COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
                      c->d_ctl, 0, c->precision, j.L.ext_col, c->stream);
+    }
     if (e == hipSuccess)
       e = launch_row(axis_phys(r->nx), ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
                      1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);

@@ -40,6 +40,7 @@ struct Vol {
   double gap_tol;
   double inv_dx, inv_dy; // 1 / voxel size (TV model's gradient)
   double knorm;          // max |D| (TV model's step check)
+  double gap_norm;       // 1 / (points of one transform): 1/(nx ny), or 1/(nx ny nz) for the 3-D kernel
   int nx, ny, nz, P;
   int half_last;      // nz odd: the last pair's imaginary part is padding
   int iters;          // iterations to run in this step (0: idle)
@@ -51,6 +52,8 @@ struct Vol {
   int check_only;     // max_iter == 0: only the gap of chi_0 = 0 is evaluated
   int check_last;     // gap partials after the step's last iteration
   int model;          // 0: L1 prior on chi, 1: weighted TV (Eq. (1))
+  int unpacked;       // 3-D kernel: one slice per complex plane (imaginary part 0), P = nz
+  int col_parts;      // column-kernel gap partial entries (P col_groups; the z view's groups in 3-D)
 };
 
 // Device-side control/result block of one resident request.  16-byte
@@ -117,7 +120,12 @@ __device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int 
   find_work_b(ranges, nranges, groups, (int)blockIdx.x, slot, pair, g);
 }
 
-enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3, COL_TV = 4 };
+// COL_FWD / COL_INV: the column transform alone (forward / inverse, in place
+// in the exchange buffer), the in-plane half of the 3-D kernel's transforms;
+// with it < 0 they run unconditionally (set-up, operator), else like
+// COL_ITER.  COL_FWD_CHK: forward, in place in the check buffer, on check steps.
+enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3, COL_TV = 4, COL_FWD = 5, COL_INV = 6,
+               COL_FWD_CHK = 7 };
 enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2, ROW_TV_DUAL = 3, ROW_TV_PRIMAL = 4 };
 
 constexpr int kThreads = 256;

@@ -86,6 +86,10 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
   } else if constexpr (MODE == COL_TV) {
     if (ctl[slot].stop || it >= V.iters) return;
+  } else if constexpr (MODE == COL_FWD || MODE == COL_INV) {
+    if (it >= 0 && (ctl[slot].stop || it >= V.iters || V.check_only)) return;
+  } else if constexpr (MODE == COL_FWD_CHK) {
+    if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
   }
   const int nx = V.nx;
   const int len = EXT == 2 ? V.ny : NY;     // true column length
@@ -100,10 +104,32 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
   __syncthreads();
   const cpx<T>* tw = tw_s;
   const cpx<T>* __restrict__ src =
-      gmem((const cpx<T>*)(MODE == COL_CHECK ? V.ex2 : V.ex)) + base + c0;
+      gmem((const cpx<T>*)(MODE == COL_CHECK || MODE == COL_FWD_CHK ? V.ex2 : V.ex)) + base + c0;
 
   cpx<T> a[F::template nq<QA>()][QA];
   cpx<T> b[F::template nq<QB>()][QB];
+  if constexpr (MODE == COL_INV) {
+    // inverse column transform alone, in place: input in the inverse's
+    // first-pass layout (QB), output in its last-pass layout (QA)
+#pragma unroll
+    for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QB; ++r) {
+        int s, n;
+        if constexpr (EXT != 0) b[q][r] = mk((T)0, (T)0);
+        if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) b[q][r] = src[(size_t)n * nx + s];
+      }
+    F::template run<+1>(b, a, lds, tw, tid, len);
+    cpx<T>* dst = gmem((cpx<T>*)V.ex) + base + c0;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QA>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QA; ++r) {
+        int s, n;
+        if (F::template pos<QA>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)n * nx + s] = a[q][r];
+      }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < F::template nq<QA>(); ++q)
 #pragma unroll
@@ -113,6 +139,18 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
       if (F::template pos<QA>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)n * nx + s];
     }
   F::template run<-1>(a, b, lds, tw, tid, len);
+  if constexpr (MODE == COL_FWD || MODE == COL_FWD_CHK) {
+    // forward column transform alone, in place
+    cpx<T>* dst = gmem((cpx<T>*)(MODE == COL_FWD_CHK ? V.ex2 : V.ex)) + base + c0;
+#pragma unroll
+    for (int q = 0; q < F::template nq<QB>(); ++q)
+#pragma unroll
+      for (int r = 0; r < QB; ++r) {
+        int s, n;
+        if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) dst[(size_t)n * nx + s] = b[q][r];
+      }
+    return;
+  }
 
   const T* __restrict__ dtab = gmem((const T*)V.dtab) + c0;
   if constexpr (MODE == COL_SETUP) {
@@ -233,14 +271,17 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   stage_twiddles(tw_s, gmem((const cpx<T>*)V.twx), F::tw_count(len), tid, kThreads);
   __syncthreads();
   const cpx<T>* tw = tw_s;
-  const bool pad_imag = V.half_last && pair == V.P - 1;
+  // imaginary part held at zero: the padding slice of an odd stack, or every
+  // plane of an unpacked (3-D kernel) volume
+  const bool pad_imag = V.unpacked || (V.half_last && pair == V.P - 1);
   const size_t plane = (size_t)len * ny;
+  const size_t slice0 = (size_t)(V.unpacked ? pair : 2 * pair);   // first caller slice of this plane
 
   cpx<T> a[F::template nq<QI>()][QI];
   cpx<T> b[F::template nq<QO>()][QO];
 
   if constexpr (MODE == ROW_FWD_PLANAR) {
-    const T* __restrict__ in = gmem((const T*)V.user_in) + (size_t)(2 * pair) * plane + (size_t)r0 * len;
+    const T* __restrict__ in = gmem((const T*)V.user_in) + slice0 * plane + (size_t)r0 * len;
 #pragma unroll
     for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
@@ -275,7 +316,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
     F::template run<+1>(a, b, lds, tw, tid, len);
 
     if constexpr (MODE == ROW_INV_PLANAR) {
-      T* __restrict__ out = gmem((T*)V.user_out) + (size_t)(2 * pair) * plane + (size_t)r0 * len;
+      T* __restrict__ out = gmem((T*)V.user_out) + slice0 * plane + (size_t)r0 * len;
 #pragma unroll
       for (int q = 0; q < F::template nq<QO>(); ++q)
 #pragma unroll
@@ -384,6 +425,9 @@ hipError_t launch_col_t(int mode, int grid, int groups, const Vol* vols, const R
     case COL_SETUP: hipLaunchKernelGGL((k_col<T, N, S, COL_SETUP, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case COL_APPLY: hipLaunchKernelGGL((k_col<T, N, S, COL_APPLY, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case COL_TV: hipLaunchKernelGGL((k_col<T, N, S, COL_TV, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_FWD: hipLaunchKernelGGL((k_col<T, N, S, COL_FWD, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_INV: hipLaunchKernelGGL((k_col<T, N, S, COL_INV, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_FWD_CHK: hipLaunchKernelGGL((k_col<T, N, S, COL_FWD_CHK, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

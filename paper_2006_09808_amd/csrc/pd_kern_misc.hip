@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Vol* __restrict__ vol
   const int slot = slots[blockIdx.x];
   const Vol& V = vols[slot];
   if (ctl[slot].stop || it != V.iters - 1 || !V.check_last) return;
-  const int nr = V.P * V.row_groups, nc = V.P * V.col_groups;
+  const int nr = V.P * V.row_groups, nc = V.col_parts;
   double l1 = 0.0, mx = 0.0, res = 0.0, yy = 0.0, yd = 0.0;
   for (int i = tid; i < nr; i += kThreads) {
     l1 += V.part_row[2 * (size_t)i];
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Vol* __restrict__ vol
     for (int w = 1; w < kThreads / 64; ++w) x = (k == 1) ? fmax(x, red[k][w]) : x + red[k][w];
     v[k] = x;
   }
-  const double invN = 1.0 / ((double)V.nx * (double)V.ny);
+  const double invN = V.gap_norm;   // Parseval: 1 / points of one transform
   const double lam = V.lam;
   const double P = 0.5 * v[2] * invN + lam * v[0];
   const double m = v[1];
@@ -181,8 +181,12 @@ __global__ __launch_bounds__(kThreads) void k_store_chi(const Vol* __restrict__ 
        i += (size_t)gridDim.x * kThreads) {
     size_t p = i / plane, o = i - p * plane;
     cpx<T> c = chi[i];
-    out[(2 * p) * plane + o] = c.x;
-    if ((int)(2 * p + 1) < nz) out[(2 * p + 1) * plane + o] = c.y;
+    if (V.unpacked) {
+      out[p * plane + o] = c.x;
+    } else {
+      out[(2 * p) * plane + o] = c.x;
+      if ((int)(2 * p + 1) < nz) out[(2 * p + 1) * plane + o] = c.y;
+    }
   }
 }
 

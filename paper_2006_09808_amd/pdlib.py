@@ -17,7 +17,8 @@ PD_OK, PD_PENDING = 0, 1
 PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET = -1, -2, -3, -4
 PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE = -5, -6, -7, -8, -9
 PD_FP32, PD_FP64 = 0, 1
-PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY = 0, 1
+PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY, PD_KERNEL_DIPOLE_3D = 0, 1, 2
+_KERNELS = {"dipole": PD_KERNEL_DIPOLE, "identity": PD_KERNEL_IDENTITY, "dipole3d": PD_KERNEL_DIPOLE_3D}
 PD_MODEL_L1, PD_MODEL_TV = 0, 1
 PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
 KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW = 0, 1, 2, 3, 4
@@ -48,7 +49,8 @@ class PdRequest(ctypes.Structure):
                 ("theta", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("gap_tol", ctypes.c_double), ("check_every", ctypes.c_int),
                 ("delta", ctypes.c_void_p), ("chi", ctypes.c_void_p),
-                ("model", ctypes.c_int), ("weight", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
+                ("model", ctypes.c_int), ("weight", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+                ("voxel_z", ctypes.c_double)]
 
 
 class PdTuneEntry(ctypes.Structure):
@@ -126,13 +128,13 @@ def now():
 
 def make_request(nx, ny, nz, delta_ptr=0, chi_ptr=0, lam=1e-3, tau=1.4, sigma=1.4, theta=1.0,
                  max_iter=200, gap_tol=0.0, check_every=10, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0),
-                 kernel="dipole", model="l1", weight_ptr=0, mask_ptr=0):
+                 kernel="dipole", model="l1", weight_ptr=0, mask_ptr=0, voxel_z=1.0):
     r = PdRequest()
     r.nx, r.ny, r.nz = int(nx), int(ny), int(nz)
     r.b0 = (ctypes.c_double * 3)(*[float(v) for v in b0])
     r.voxel = (ctypes.c_double * 2)(*[float(v) for v in voxel])
-    r.kernel = {"dipole": PD_KERNEL_DIPOLE, "identity": PD_KERNEL_IDENTITY}[kernel] \
-        if isinstance(kernel, str) else int(kernel)
+    r.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    r.voxel_z = float(voxel_z)
     r.lam, r.tau, r.sigma, r.theta = float(lam), float(tau), float(sigma), float(theta)
     r.max_iter, r.gap_tol, r.check_every = int(max_iter), float(gap_tol), int(check_every)
     r.delta, r.chi = int(delta_ptr) or None, int(chi_ptr) or None
@@ -153,8 +155,8 @@ def validate(nx, ny, nz, precision="fp32", **params):
     return int(nbytes.value)
 
 
-def kernel_norm(nx, ny, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole"):
-    r = make_request(nx, ny, 1, b0=b0, voxel=voxel, kernel=kernel)
+def kernel_norm(nx, ny, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole", nz=1, voxel_z=1.0):
+    r = make_request(nx, ny, nz, b0=b0, voxel=voxel, kernel=kernel, voxel_z=voxel_z)
     out = ctypes.c_double(0.0)
     st = load_library().pd_kernel_norm(ctypes.byref(r), ctypes.byref(out))
     if st != PD_OK:
@@ -272,14 +274,16 @@ class Solver:
             raise PdError(info["status"], "solve")
         return chi, info
 
-    def apply_kernel(self, x, out=None, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole"):
-        """out = A x slice by slice (the field map of susceptibility x)."""
+    def apply_kernel(self, x, out=None, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole", voxel_z=1.0):
+        """out = A x (the field map of susceptibility x): slice by slice, or
+        over the whole volume for kernel="dipole3d"."""
         self._check_tensor(x, "x")
         if out is None:
             out = self._torch.empty_like(x)
         self._check_tensor(out, "out")
         nz, ny, nx = x.shape
-        r = make_request(nx, ny, nz, x.data_ptr(), out.data_ptr(), b0=b0, voxel=voxel, kernel=kernel)
+        r = make_request(nx, ny, nz, x.data_ptr(), out.data_ptr(), b0=b0, voxel=voxel, kernel=kernel,
+                         voxel_z=voxel_z)
         self._torch.cuda.current_stream(self.device).synchronize()
         st = self.lib.pd_apply_kernel(self._ctx, ctypes.byref(r))
         if st != PD_OK:

@@ -183,3 +183,30 @@ def test_ctypes_structs_match_the_c_layout(tmp_path):
         assert got[(sname, "size")] == ctypes.sizeof(cls), sname
         for fname, _ in cls._fields_:
             assert got[(sname, fname)] == getattr(cls, fname).offset, (sname, fname)
+
+
+@pytest.mark.parametrize("nx,ny,nz,b0,vox,dz", [(8, 8, 4, (0, 1, 0), (1, 1), 1.0), (12, 6, 5, (0.3, 0.5, 0.8), (0.8, 1.2), 2.0),
+                                                (16, 16, 8, (0, 0, 1), (1, 1), 1.5)])
+def test_kernel_norm_3d_matches_oracle(nx, ny, nz, b0, vox, dz):
+    D = oracle.dipole_kernel3(nx, ny, nz, b0, vox, dz)
+    got = pd.kernel_norm(nx, ny, b0, vox, kernel="dipole3d", nz=nz, voxel_z=dz)
+    assert got == pytest.approx(oracle.kernel_norm(D), abs=1e-15)
+
+
+def test_3d_kernel_request_rules():
+    k3 = dict(kernel="dipole3d", voxel_z=1.0)
+    nb2 = pd.validate(64, 64, 8)
+    nb3 = pd.validate(64, 64, 8, **k3)
+    assert nb3 > nb2                       # unpacked planes and the 3-D D table
+    assert pd.validate(64, 64, 43, **k3) > 0          # Bluestein along z
+    for bad, status in ((dict(voxel_z=0.0), pd.PD_ERR_ARG), (dict(voxel_z=float("nan")), pd.PD_ERR_ARG),
+                        (dict(model="tv", weight_ptr=3, mask_ptr=4, lam=10.0), pd.PD_ERR_ARG)):
+        with pytest.raises(pd.PdError) as e:
+            pd.validate(64, 64, 8, **dict(k3, **bad))
+        assert e.value.status == status
+    for nz in (1, 385):
+        with pytest.raises(pd.PdError) as e:
+            pd.validate(64, 64, nz, **k3)
+        assert e.value.status == pd.PD_ERR_SIZE
+    # the 2-D kernel ignores voxel_z
+    pd.validate(64, 64, 1, voxel_z=0.0)
