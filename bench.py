@@ -300,6 +300,44 @@ def tv_workload(nz=64, n=256, iters=500, reps=3):
     return out
 
 
+def volume3d_workload(nz=64, n=256, iters=500, reps=3):
+    """The 3-D dipole kernel (whole-volume operator, slices coupled) on nz
+    slices of n x n: wall time per solve (steps replayed from HIP graphs) and
+    the HIP-event time of its kernel classes on a second context."""
+    import torch
+    import pd_inputs
+    import paper_2006_09808_amd as pd
+    dev = torch.device("cuda", 0)
+    w = pd_inputs.random_stack(6100, nz, n, n, lam=1e-3, max_iter=iters)
+    sp = dict(w.solver_params(), kernel="dipole3d", voxel_z=2.0)
+    with pd.Solver(arena_bytes=4 << 30, device=0) as s:
+        field = s.apply_kernel(torch.from_numpy(w.chi_true.astype(np.float32)).to(dev), kernel="dipole3d",
+                               voxel_z=2.0)
+        d = torch.from_numpy(pd_inputs.make_delta(field.cpu().numpy().astype(np.float64), w.eta, w.rho)
+                             .astype(np.float32)).to(dev)
+        chi = torch.empty_like(d)
+        best = None
+        for i in range(reps + 2):
+            t0 = pd.now()
+            r = s.poll(s.submit([(d, chi, sp)])[0], -1)
+            if r["status"] != pd.PD_OK or r["iterations"] != iters:
+                raise RuntimeError("3-D solve failed: %r" % (r,))
+            dt = pd.now() - t0
+            if i >= 2:
+                best = dt if best is None else min(best, dt)
+    with pd.Solver(arena_bytes=4 << 30, device=0, time_kernels=True) as s:
+        s.poll(s.submit([(d, chi, sp)])[0], -1)
+        kt = {name: s.kernel_time(kind) for name, kind in
+              (("plane_column", pd.KIND_COLUMN), ("plane_row", pd.KIND_ROW), ("z_transform", pd.KIND_Z))}
+    vit = nz * n * n * iters
+    out = {"workload": "3-D dipole kernel, %d slices of %dx%d, %d iterations" % (nz, n, n, iters),
+           "ms": best * 1e3, "voxel_iterations_per_s": vit / best, "kernels": {}}
+    for name, (nl, ms, pts) in kt.items():
+        if nl:
+            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl}
+    return out
+
+
 def cpu_baseline(w, nslices, iters):
     """FP64 oracle on a bounded sample of the same workload (first `nslices`
     slices, `iters` iterations), on this host's cores."""
@@ -450,6 +488,7 @@ def main():
     if not a.no_workloads:
         out["workloads"] = other_workloads()
         out["workloads"]["tv_256x256x64_500it"] = tv_workload()
+        out["workloads"]["dipole3d_256x256x64_500it"] = volume3d_workload()
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
     if not a.no_cpu_baseline:

@@ -211,7 +211,9 @@ double pd_now(void);
  * iterations of square slices kept on chip), 3 = TV-model column kernel
  * (forward column FFT, multiply by D, inverse column FFT; two per iteration),
  * 4 = TV-model row kernels (inverse row FFT, dual or primal update, forward
- * row FFT; two per iteration).  pd_kernel_time_reset clears all. */
+ * row FFT; two per iteration), 5 = the 3-D kernel's z transform (forward z
+ * FFT, dual prox, inverse z FFT; kind 0 then counts its in-plane column
+ * transforms).  pd_kernel_time_reset clears all. */
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 
