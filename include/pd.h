@@ -250,7 +250,11 @@ pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* c
  * steps replayed from one, since pd_create. */
 pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays);
 
-/* Bytes of arena currently in use and the number of resident requests. */
+/* Bytes of arena currently in use (control blocks, resident requests' state,
+ * and kernel tables: D grid and twiddles per kernel shape, which stay cached
+ * after their last request retires and are evicted, least recently used
+ * first, when an admission needs the space), the number of resident requests
+ * and the number of queued ones. */
 pd_status pd_arena_usage(pd_ctx* c, size_t* used, int* resident, int* queued);
 
 #ifdef __cplusplus

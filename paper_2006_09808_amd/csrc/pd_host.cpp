@@ -41,6 +41,7 @@ constexpr int kDefaultStep = 500;       // step cap while no request waits for a
 constexpr int kQueuedStep = 50;         // step cap while requests wait in the queue
 constexpr int kMaxStep = 1 << 20;
 constexpr int kMaxGraphs = 32;
+constexpr double kIdleSpin = 200e-6;    // seconds the idle worker polls the queue before sleeping
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 inline bool isfin(double x) { return std::isfinite(x); }
@@ -316,6 +317,48 @@ pd_status kernel_args(const pd_request* r) {
   return PD_OK;
 }
 
+// max |D| per kernel grid, cached: validation runs on every submission and
+// the grid has nx ny (nz) points
+double cached_kernel_norm(const pd_request* r) {
+  struct Key {
+    int nx, ny, nz3, kernel;
+    double b[3], vox[2], vz;
+    bool operator<(const Key& o) const {
+      return std::memcmp(this, &o, sizeof(Key)) < 0;
+    }
+  };
+  static std::mutex mu;
+  static std::map<Key, double> cache;
+  Key k;
+  std::memset(&k, 0, sizeof(k));   // padding takes part in the comparison
+  k.nx = r->nx;
+  k.ny = r->ny;
+  k.nz3 = r->kernel == PD_KERNEL_DIPOLE_3D ? r->nz : 0;
+  k.kernel = r->kernel;
+  if (r->kernel != PD_KERNEL_IDENTITY) unit_b0(r->b0, k.b);
+  k.vox[0] = r->voxel[0];
+  k.vox[1] = r->voxel[1];
+  k.vz = k.nz3 ? r->voxel_z : 0.0;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(k);
+    if (it != cache.end()) return it->second;
+  }
+  double L = 0.0;
+  if (r->kernel == PD_KERNEL_DIPOLE_3D) {
+    dipole_grid3(r->nx, r->ny, r->nz, r->b0, r->voxel, r->voxel_z,
+                 [&](size_t, double d) { L = std::max(L, std::fabs(d)); });
+  } else {
+    std::vector<double> D;
+    dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
+    L = grid_norm(D);
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (cache.size() > 4096) cache.clear();
+  cache[k] = L;
+  return L;
+}
+
 pd_status validate(const pd_request* r, int precision, double* norm_out) {
   if (!r) return PD_ERR_ARG;
   if (precision != PD_FP32 && precision != PD_FP64) return PD_ERR_ARG;
@@ -336,15 +379,7 @@ pd_status validate(const pd_request* r, int precision, double* norm_out) {
   }
   if (!isfin(r->tau) || !isfin(r->sigma) || r->tau <= 0 || r->sigma <= 0) return PD_ERR_STEP;
   if (!isfin(r->theta) || r->theta < 0 || r->theta > 1) return PD_ERR_STEP;
-  double L = 0.0;
-  if (r->kernel == PD_KERNEL_DIPOLE_3D) {
-    dipole_grid3(r->nx, r->ny, r->nz, r->b0, r->voxel, r->voxel_z,
-                 [&](size_t, double d) { L = std::max(L, std::fabs(d)); });
-  } else {
-    std::vector<double> D;
-    dipole_grid(r->nx, r->ny, r->b0, r->voxel, r->kernel, D);
-    L = grid_norm(D);
-  }
+  const double L = cached_kernel_norm(r);
   // the TV model's condition also needs max|W| and max|M|: tested on the
   // device at admission
   if (r->model == PD_MODEL_L1 && !(r->tau * r->sigma * L * L < 1.0)) return PD_ERR_STEP;
@@ -426,6 +461,7 @@ struct TableKey {
 struct Table {
   size_t off = 0, bytes = 0;
   int refs = 0;
+  uint64_t last_use = 0;
   bool uploaded = false;
   void *d = nullptr, *twx = nullptr, *twy = nullptr, *twz = nullptr;
 };
@@ -471,6 +507,7 @@ struct pd_ctx {
   std::mutex exec_mu;          // GPU submission (worker steps vs. pd_apply_kernel)
   Arena arena;
   std::map<TableKey, Table> tables;
+  uint64_t table_clock = 0;
   std::deque<std::shared_ptr<Job>> queue;
   std::vector<std::shared_ptr<Job>> active;
   std::map<uint64_t, std::shared_ptr<Job>> jobs;
@@ -485,6 +522,7 @@ struct pd_ctx {
   size_t ctl_off = 0, ctl_bytes = 0;
   Vol* d_vols = nullptr;       // 2 (nslots + 1): plane views, then the 3-D kernel's z views from zoff
   int zoff = 0;
+  std::atomic<int> n_queued{0};   // queue length, readable without the lock (worker's idle spin)
   Ctl* d_ctl = nullptr;        // nslots + 1
   int* d_slots = nullptr;      // nslots
   Range* d_ranges = nullptr;   // range_cap
@@ -533,17 +571,41 @@ bool hip_ok(pd_ctx* c, hipError_t e) {
   return false;
 }
 
+// Tables whose last user has retired stay in the arena (uploaded), so the
+// next request of that kernel shape starts without rebuilding them; they are
+// evicted, least recently used first, when an allocation needs the space.
+// Caller holds c->mu.  Returns false if no unused table is left.
+bool evict_unused_table(pd_ctx* c) {
+  auto victim = c->tables.end();
+  for (auto it = c->tables.begin(); it != c->tables.end(); ++it)
+    if (it->second.refs == 0 && (victim == c->tables.end() || it->second.last_use < victim->second.last_use))
+      victim = it;
+  if (victim == c->tables.end()) return false;
+  c->arena.release(victim->second.off, victim->second.bytes);
+  c->tables.erase(victim);
+  return true;
+}
+
+// Arena allocation that evicts unused tables while it does not fit.
+bool arena_alloc(pd_ctx* c, size_t bytes, size_t* off) {
+  while (!c->arena.alloc(bytes, off))
+    if (!evict_unused_table(c)) return false;
+  return true;
+}
+
 // Acquire (or share) the table of a shape; caller holds c->mu.
 Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
   auto it = c->tables.find(k);
   if (it != c->tables.end()) {
     it->second.refs++;
+    it->second.last_use = ++c->table_clock;
     *fresh = false;
     return &it->second;
   }
   Table t;
   t.bytes = table_bytes(k.nx, k.ny, k.nz3, c->precision);
-  if (!c->arena.alloc(t.bytes, &t.off)) return nullptr;
+  if (!arena_alloc(c, t.bytes, &t.off)) return nullptr;
+  t.last_use = ++c->table_clock;
   size_t tsz = c->precision == PD_FP64 ? 8 : 4;
   char* p = c->arena.ptr(t.off);
   t.d = p;
@@ -559,10 +621,7 @@ Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
 void release_table(pd_ctx* c, const TableKey& k) {
   auto it = c->tables.find(k);
   if (it == c->tables.end()) return;
-  if (--it->second.refs == 0) {
-    c->arena.release(it->second.off, it->second.bytes);
-    c->tables.erase(it);
-  }
+  --it->second.refs;   // at zero the table stays cached (evict_unused_table)
 }
 
 template <typename T>
@@ -701,7 +760,7 @@ void fill_zvol(const Job& j, const Vol& V, Vol& Z) {
 bool reserve(pd_ctx* c, Job& j) {
   if (c->free_slots.empty()) return false;
   size_t off;
-  if (!c->arena.alloc(j.L.total, &off)) return false;
+  if (!arena_alloc(c, j.L.total, &off)) return false;
   bool fresh = false;
   Table* t = acquire_table(c, j.key, &fresh);
   if (!t) {
@@ -1197,12 +1256,23 @@ void worker_main(pd_ctx* c) {
   (void)hipSetDevice(c->device);
   std::unique_lock<std::mutex> lk(c->mu);
   while (true) {
-    c->cv_work.wait(lk, [&] { return c->stopping || !c->queue.empty() || !c->active.empty(); });
+    auto has_work = [&] { return c->stopping || !c->queue.empty() || !c->active.empty(); };
+    if (!has_work()) {
+      // idle: poll the queue length for a short while before sleeping, so a
+      // request that arrives soon starts without a thread wake-up
+      lk.unlock();
+      const double t_idle = now_s();
+      while (c->n_queued.load(std::memory_order_acquire) == 0 && now_s() - t_idle < kIdleSpin)
+        std::this_thread::yield();
+      lk.lock();
+      c->cv_work.wait(lk, has_work);
+    }
     if (c->stopping) break;
     if (c->poisoned != PD_OK) {
       for (auto& j : c->queue) finish_job(c, *j, c->poisoned);
       for (auto& j : c->active) finish_job(c, *j, c->poisoned);
       c->queue.clear();
+      c->n_queued.store(0, std::memory_order_relaxed);
       c->active.clear();
       c->cv_done.notify_all();
       continue;
@@ -1213,6 +1283,7 @@ void worker_main(pd_ctx* c) {
       auto j = c->queue.front();
       if (!reserve(c, *j)) break;
       c->queue.pop_front();
+      c->n_queued.fetch_sub(1, std::memory_order_relaxed);
       admitted.push_back(j);
     }
     std::vector<std::pair<TableKey, Table>> uploads;
@@ -1458,6 +1529,7 @@ pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* ticket
     tickets[i] = js[i]->ticket;
     c->jobs[js[i]->ticket] = js[i];
     c->queue.push_back(js[i]);
+    c->n_queued.fetch_add(1, std::memory_order_release);
   }
   c->cv_work.notify_all();
   return PD_OK;
@@ -1532,7 +1604,7 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->poisoned != PD_OK) return c->poisoned;
     size_t off;
-    if (!c->arena.alloc(j.L.total, &off)) return PD_ERR_BUDGET;
+    if (!arena_alloc(c, j.L.total, &off)) return PD_ERR_BUDGET;
     Table* t = acquire_table(c, j.key, &fresh);
     if (!t) {
       c->arena.release(off, j.L.total);
@@ -1641,7 +1713,7 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->poisoned != PD_OK) return c->poisoned;
     size_t off;
-    if (!c->arena.alloc(j.L.total, &off)) return PD_ERR_BUDGET;
+    if (!arena_alloc(c, j.L.total, &off)) return PD_ERR_BUDGET;
     Table* t = acquire_table(c, j.key, &fresh);
     if (!t) {
       c->arena.release(off, j.L.total);
