@@ -139,3 +139,34 @@ def test_3d_and_2d_volumes_in_one_batch_equal_their_solo_runs(solver, torch_mod)
         (t,) = solver.submit([(d, solo, params)])
         assert solver.poll(t, -1)["status"] == 0
         np.testing.assert_array_equal(solo.cpu().numpy(), ref)
+
+
+def test_l1_solve_3d_fp64_matches_oracle(solver64, torch_mod):
+    nx, ny, nz, b0, vox, dz = SHAPES[3]         # Bluestein along x and z
+    sp, delta = make_case3(321, nz, ny, nx, b0, vox, dz, max_iter=25)
+    d = torch_mod.from_numpy(delta.astype(np.float64)).to("cuda:0")
+    chi, info = solver64.solve(d, kernel="dipole3d", voxel_z=dz, **sp)
+    ref, rinfo = oracle.solve(delta.astype(np.float64), kind="dipole3d", voxel_z=dz, **sp)
+    err = rel_l2(chi.cpu().numpy(), ref)
+    _say("fp64 3-D solve relL2 %.3e" % err)
+    assert err <= 1e-10
+    assert info["rel_gap"] == pytest.approx(rinfo["rel_gap"], rel=1e-9)
+
+
+def test_gap_tolerance_stop_3d(solver, torch_mod):
+    # a weak field relative to lambda: the gap reaches the tolerance within the
+    # cap and both sides stop at (nearly) the same check
+    rng = np.random.default_rng(330)
+    nx, ny, nz, dz = 32, 32, 8, 1.0
+    x = np.zeros((nz, ny, nx))
+    x[2:5, 10:14, 12:15] = 1.0
+    delta = (oracle.forward(x, kind="dipole3d", voxel_z=dz) + 0.01 * rng.normal(size=x.shape)).astype(np.float32)
+    sp = dict(lam=0.05, tau=1.4, sigma=1.4, theta=1.0, max_iter=600, gap_tol=1e-3, check_every=10)
+    d = torch_mod.from_numpy(delta).to("cuda:0")
+    chi, info = solver.solve(d, kernel="dipole3d", voxel_z=dz, **sp)
+    ref, rinfo = oracle.solve(delta.astype(np.float64), kind="dipole3d", voxel_z=dz, **sp)
+    _say("3-D gap stop: gpu %d it relgap %.3e; oracle %d it relgap %.3e" % (
+        info["iterations"], info["rel_gap"], rinfo["iterations"], rinfo["rel_gap"]))
+    assert rinfo["iterations"] < 600
+    assert abs(info["iterations"] - rinfo["iterations"]) <= 10
+    assert info["rel_gap"] <= 1e-3

@@ -169,3 +169,28 @@ def test_mixed_sizes_in_one_batch_equal_their_solo_runs(solver, torch_mod):
         (t,) = solver.submit([(d, solo, params)])
         assert solver.poll(t, -1)["status"] == 0
         np.testing.assert_array_equal(solo.cpu().numpy(), ref)
+
+
+def test_l1_solve_bluestein_fp64(solver64, torch_mod):
+    w, delta = make_case(221, 3, 43, 100, max_iter=30)
+    sp = w.solver_params()
+    d = torch_mod.from_numpy(delta.astype(np.float64)).to("cuda:0")
+    chi, info = solver64.solve(d, **sp)
+    ref, rinfo = oracle.solve(delta.astype(np.float64), **sp)
+    err = rel_l2(chi.cpu().numpy(), ref)
+    _say("fp64 bluestein solve relL2 %.3e" % err)
+    assert err <= 1e-10
+    assert info["rel_gap"] == pytest.approx(rinfo["rel_gap"], rel=1e-9)
+
+
+def test_tv_solve_bluestein_odd_stack(solver, torch_mod):
+    from test_gpu_tv import make_tv_case, gpu_tv_solve
+    # 43 x 27 slices (both axes Bluestein, partial tiles), 5 slices (padded pair)
+    w, delta, W, M = make_tv_case(222, 5, 27, 43, b0=(0.3, 0.5, 0.8), voxel=(0.8, 1.2), iters=35)
+    sp = w.solver_params()
+    chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
+    assert info["status"] == 0
+    ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
+    err = rel_l2(chi, ref)
+    _say("tv 43x27x5 relL2 %.3e" % err)
+    assert err <= REL_TOL
