@@ -200,6 +200,8 @@ def other_workloads(reps=20):
                                        "solves": len(lat)}
     vols = pd_inputs.config3()
     with pd.Solver(arena_bytes=8 << 30, device=0) as s:
+        for w in vols:                       # autotune each shape at its own slice count
+            s.tune(w.shape[2], w.shape[1], w.shape[0], iters=50)
         jobs = []
         for w in vols:
             d = _device_delta(s, w, dev)
