@@ -106,10 +106,17 @@ typedef struct {
   size_t arena_bytes;
   int max_slots;       /* most requests resident on the GPU at once; 0 = no cap  */
   int precision;       /* PD_FP32 (default) or PD_FP64                            */
-  int step_iters;      /* most iterations launched between host scheduling points
-                          (requests are admitted and retired only there); a step
-                          also ends at every request's next gap check; 0 = 500,
-                          or 50 while requests wait in the queue                 */
+  int step_iters;      /* most iterations of one step (one resident launch, or one
+                          captured graph of the two-launch path); a step also
+                          ends at every request's next gap check; 0 = 500, or 50
+                          while requests wait in the queue.  Requests are
+                          admitted and retired between rounds: while none waits,
+                          a round enqueues up to 8 steps (100 iterations, or up
+                          to some request's last iteration) before the host
+                          reads the stop flags; otherwise one step.  A volume
+                          whose gap check stops it mid-round is skipped by the
+                          round's later steps, so results do not depend on the
+                          round length.                                          */
   int flags;           /* PD_FLAG_* */
 } pd_config;
 

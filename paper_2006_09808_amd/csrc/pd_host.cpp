@@ -41,6 +41,12 @@ constexpr int kDefaultStep = 500;       // step cap while no request waits for a
 constexpr int kQueuedStep = 50;         // step cap while requests wait in the queue
 constexpr int kMaxStep = 1 << 20;
 constexpr int kMaxGraphs = 32;
+// run-ahead: while no request waits, a round enqueues up to kRunAhead steps
+// (stopping at kRunAheadIters iterations or at any volume's last iteration)
+// before the host waits once; kernels skip volumes whose gap check already
+// stopped them, so the steps after a stop cost a few empty launches only
+constexpr int kRunAhead = 8;
+constexpr int kRunAheadIters = 100;
 constexpr double kIdleSpin = 200e-6;    // seconds the idle worker polls the queue before sleeping
 
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -476,6 +482,7 @@ struct Job {
   TableKey key{};
   Table tab{};              // copy of the shared table's device pointers
   int done_iters = 0;
+  int run_iters = 0;        // iterations enqueued for it in the current round
   bool finished = false;
   double knorm = 0.0;       // max |D| of the request's kernel grid
   pd_result res{};
@@ -518,8 +525,14 @@ struct pd_ctx {
   std::thread worker;
 
   // control arrays: device copies carved from the arena, pinned host mirrors.
-  // Entry nslots of vols/ctl/ranges is reserved for pd_apply_kernel.
+  // Entry nslots of vols/ctl/ranges is reserved for pd_apply_kernel.  The
+  // step block [vols][slots][ranges] is contiguous on the device, so a step
+  // uploads it in one copy from a pinned image of the same layout; likewise
+  // [ctl][abort] comes back in one copy per round.
   size_t ctl_off = 0, ctl_bytes = 0;
+  size_t off_slots = 0, off_ranges = 0;   // offsets inside the step block
+  size_t off_abort = 0;                   // offset of the abort word after the ctl array
+  char* h_stage[kRunAhead] = {};          // pinned step-block images, one per step of a round
   Vol* d_vols = nullptr;       // 2 (nslots + 1): plane views, then the 3-D kernel's z views from zoff
   int zoff = 0;
   std::atomic<int> n_queued{0};   // queue length, readable without the lock (worker's idle spin)
@@ -529,10 +542,9 @@ struct pd_ctx {
   size_t range_cap = 0;        // entries of d_ranges / h_ranges; the last is pd_apply_kernel's
   unsigned* d_counters = nullptr;   // resident-launch counters, counter_bytes(kMaxTeamSlots)
   int* d_abort = nullptr;           // set by a resident launch whose barrier timed out
-  int* h_abort = nullptr;
-  Vol* h_vols = nullptr;
+  int* h_abort = nullptr;      // inside the h_ctl block
+  Vol* h_vols = nullptr;       // host mirror of the descriptors (set-up, operator and tuner paths)
   Ctl* h_ctl = nullptr;
-  int* h_slots = nullptr;
   Range* h_ranges = nullptr;
 
   // autotuned choices per slice shape (nx, ny): resident variant and the
@@ -793,6 +805,18 @@ hipEvent_t get_event(pd_ctx* c) {
   return e;
 }
 
+void free_host(pd_ctx* c) {
+  if (c->h_vols) (void)hipHostFree(c->h_vols);
+  if (c->h_ctl) (void)hipHostFree(c->h_ctl);   // holds h_abort too
+  if (c->h_ranges) (void)hipHostFree(c->h_ranges);
+  for (char*& b : c->h_stage)
+    if (b) (void)hipHostFree(b);
+  c->h_vols = nullptr;
+  c->h_ctl = nullptr;
+  c->h_ranges = nullptr;
+  c->h_abort = nullptr;
+}
+
 // ---------------------------------------------------------------------------
 // set-up of a newly admitted job: zero state, F delta, zero partials
 // ---------------------------------------------------------------------------
@@ -857,19 +881,34 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
   return hipStreamSynchronize(c->stream);
 }
 
+// HIP events of timed launches, read back after a round
+struct StepEvents {
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
+  std::vector<double> points;
+};
+
 // One scheduling step over all resident jobs: K iterations for every job,
 // where K ends the step at every job's next gap check (or its last
-// iteration), so checks and stop decisions only happen at step ends.
-hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued) {
+// iteration), so checks and stop decisions only happen at step ends.  Each
+// job starts the step at done_iters + run_iters (the steps already enqueued
+// in this round).  The step's descriptors, slot list and range table are
+// written to the pinned image `stage` and uploaded in one copy.  `last`: some
+// job runs its last iteration (or only its check) in this step.
+hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued, char* stage,
+                        StepEvents& tev, int& K_out, bool& last) {
   int K = c->cfg.step_iters > 0 ? c->cfg.step_iters : (queued ? kQueuedStep : kDefaultStep);
+  Vol* s_vols = (Vol*)stage;
+  int* s_slots = (int*)(stage + c->off_slots);
+  Range* s_ranges = (Range*)(stage + c->off_ranges);
   bool any_check_only = false;
   for (auto& j : act) {
     if (j->req.max_iter == 0) {
       any_check_only |= !j->L.tv;   // a TV volume with no iteration just retires
       continue;
     }
-    int rem = j->req.max_iter - j->done_iters;
-    int nc = j->req.gap_tol > 0 ? j->req.check_every - j->done_iters % j->req.check_every : rem;
+    const int done = j->done_iters + j->run_iters;
+    int rem = j->req.max_iter - done;
+    int nc = j->req.gap_tol > 0 ? j->req.check_every - done % j->req.check_every : rem;
     K = std::min(K, std::min(rem, nc));
   }
   if (any_check_only) K = 1;
@@ -879,14 +918,16 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   std::map<GroupKey, std::vector<Job*>> groups;
   int nslot_list = 0;
   bool any_check = false;
+  last = false;
   for (auto& j : act) {
     groups[GroupKey{j->req.nx, j->req.ny, j->req.model, nz3_of(j->req)}].push_back(j.get());
     Vol& V = c->h_vols[j->slot];
     fill_vol(c, *j, V);
+    const int done = j->done_iters + j->run_iters;
     if (j->L.tv) {                  // fixed iteration count, no gap checks
-      int rem = j->req.max_iter - j->done_iters;
+      int rem = j->req.max_iter - done;
       V.iters = std::min(K, rem);
-      V.done_base = j->done_iters;
+      V.done_base = done;
       V.final_it = (rem == V.iters) ? V.iters - 1 : -1;
       V.check_last = 0;
     } else if (j->req.max_iter == 0) {     // check-only step: gap of chi_0 = 0, y_0 = 0
@@ -896,15 +937,16 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
       V.check_last = 1;
       V.check_only = 1;
     } else {
-      int rem = j->req.max_iter - j->done_iters;
+      int rem = j->req.max_iter - done;
       V.iters = std::min(K, rem);
-      V.done_base = j->done_iters;
+      V.done_base = done;
       V.final_it = (rem == V.iters) ? V.iters - 1 : -1;
-      int n = j->done_iters + V.iters;
+      int n = done + V.iters;
       V.check_last = (j->req.gap_tol > 0 && n % j->req.check_every == 0) || n == j->req.max_iter;
     }
+    last |= V.final_it >= 0 || V.iters <= 0;
     any_check |= V.check_last != 0;
-    c->h_slots[nslot_list++] = j->slot;
+    s_slots[nslot_list++] = j->slot;
   }
 
   // launch plan: per shape either one resident launch per batch of pairs that
@@ -925,7 +967,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   size_t k = 0;
   auto push_range = [&](int slot, int first, int pair0) -> bool {
     if (k + 1 >= c->range_cap) return false;
-    c->h_ranges[k++] = Range{slot, first, pair0, 0};
+    s_ranges[k++] = Range{slot, first, pair0, 0};
     return true;
   };
   bool fits = true;
@@ -1019,28 +1061,30 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   for (auto& L : launches)
     if (L.resident)
       for (int i = 0; i < L.nranges; ++i) {
-        Vol& V = c->h_vols[c->h_ranges[L.range_off + i].slot];
+        Vol& V = c->h_vols[s_ranges[L.range_off + i].slot];
         V.row_groups = V.col_groups = L.team;
       }
   for (auto& j : act) {
     Vol& V = c->h_vols[j->slot];
     V.col_parts = j->L.unpacked ? j->L.zgroups : V.P * V.col_groups;
-    if (j->L.unpacked) fill_zvol(*j, V, c->h_vols[c->zoff + j->slot]);
+    s_vols[j->slot] = V;
+    if (j->L.unpacked) {
+      fill_zvol(*j, V, c->h_vols[c->zoff + j->slot]);
+      s_vols[c->zoff + j->slot] = c->h_vols[c->zoff + j->slot];
+    }
+    j->run_iters += std::max(V.iters, 0);
   }
+  K_out = K;
 
+  // descriptors of idle slots in the image are stale: no launch of this
+  // step reads them (ranges and the slot list name active jobs only)
   hipError_t e;
-  if ((e = hipMemcpyAsync(c->d_ranges, c->h_ranges, sizeof(Range) * k, hipMemcpyHostToDevice, c->stream)) !=
-      hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipMemcpyHostToDevice,
-                          c->stream)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(c->d_slots, c->h_slots, sizeof(int) * nslot_list, hipMemcpyHostToDevice,
+  if ((e = hipMemcpyAsync(c->d_vols, stage, c->off_ranges + sizeof(Range) * k, hipMemcpyHostToDevice,
                           c->stream)) != hipSuccess)
     return e;
 
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
-  std::vector<double> ev_points;
+  auto& evs = tev.evs;
+  auto& ev_points = tev.points;
   auto timed = [&](int kind, double points, auto&& fn) -> hipError_t {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->time_kernels) {
@@ -1220,26 +1264,42 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   } else if ((e = enqueue_rest(c->time_kernels)) != hipSuccess) {
     return e;
   }
-  if ((e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl) * c->nslots, hipMemcpyDeviceToHost, c->stream)) !=
-      hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(c->h_abort, c->d_abort, sizeof(int), hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
-    return e;
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return e;
-  if (!evs.empty()) {
+  return hipSuccess;
+}
+
+// One scheduling round: steps enqueued back to back (run-ahead, while no
+// request waits for admission), then one read-back of every volume's control
+// block and one wait.  Returns with run_iters = iterations enqueued per job.
+hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued) {
+  for (auto& j : act) j->run_iters = 0;
+  StepEvents tev;
+  hipError_t e = hipSuccess;
+  int total = 0;
+  for (int s = 0; s < kRunAhead; ++s) {
+    int K = 0;
+    bool last = false;
+    if ((e = enqueue_step(c, act, queued, c->h_stage[s], tev, K, last)) != hipSuccess) break;
+    total += K;
+    if (last || queued || total >= kRunAheadIters) break;
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->h_ctl, c->d_ctl, c->off_abort + sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (!tev.evs.empty()) {
     std::lock_guard<std::mutex> lk(c->tmu);
-    for (size_t i = 0; i < evs.size(); ++i) {
-      auto& x = evs[i];
+    for (size_t i = 0; i < tev.evs.size(); ++i) {
+      auto& x = tev.evs[i];
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
+      if (e == hipSuccess && hipEventElapsedTime(&ms, x.second.first, x.second.second) == hipSuccess) {
         c->t_launches[x.first]++;
         c->t_ms[x.first] += ms;
-        c->t_points[x.first] += ev_points[i];
+        c->t_points[x.first] += tev.points[i];
       }
       c->ev_pool.push_back(x.second.first);
       c->ev_pool.push_back(x.second.second);
     }
   }
+  if (e != hipSuccess) return e;
   if (*c->h_abort) return hipErrorLaunchTimeOut;   // a team barrier gave up
   return hipSuccess;
 }
@@ -1328,11 +1388,10 @@ void worker_main(pd_ctx* c) {
       if (e == hipSuccess) {
         for (auto& j : act) {
           const Ctl& C = c->h_ctl[j->slot];
-          Vol& V = c->h_vols[j->slot];
           // the final check always stops a volume; the cap test only guards
           // against a step that could not run it
-          if (C.stop || ((j->req.max_iter > 0 || j->L.tv) && j->done_iters + V.iters >= j->req.max_iter)) {
-            j->res.iterations = C.stop ? C.stop_iter : j->done_iters + V.iters;
+          if (C.stop || ((j->req.max_iter > 0 || j->L.tv) && j->done_iters + j->run_iters >= j->req.max_iter)) {
+            j->res.iterations = C.stop ? C.stop_iter : j->done_iters + j->run_iters;
             if (j->L.tv) {   // no duality gap is defined for the TV model
               j->res.primal = j->res.dual = j->res.rel_gap = std::nan("");
             } else {
@@ -1352,7 +1411,7 @@ void worker_main(pd_ctx* c) {
             }
             if (e != hipSuccess) break;
           } else {
-            j->done_iters += V.iters;
+            j->done_iters += j->run_iters;
           }
         }
         if (e == hipSuccess && !retired.empty()) e = hipStreamSynchronize(c->stream);
@@ -1442,22 +1501,21 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
 
   c->range_cap = 4 * (size_t)c->nslots + 4096;
   c->zoff = c->nslots + 1;
-  c->ctl_bytes = align_up(sizeof(Vol) * 2 * (c->nslots + 1)) + align_up(sizeof(Ctl) * (c->nslots + 1)) +
-                 align_up(sizeof(int) * c->nslots) + align_up(sizeof(Range) * c->range_cap) +
-                 align_up(counter_bytes(kMaxTeamSlots)) + align_up(sizeof(int));
+  c->off_slots = align_up(sizeof(Vol) * 2 * (c->nslots + 1));
+  c->off_ranges = c->off_slots + align_up(sizeof(int) * c->nslots);
+  c->off_abort = align_up(sizeof(Ctl) * (c->nslots + 1));
+  const size_t step_block = c->off_ranges + sizeof(Range) * c->range_cap;
+  c->ctl_bytes = align_up(step_block) + align_up(c->off_abort + sizeof(int)) + align_up(counter_bytes(kMaxTeamSlots));
   if (!c->arena.alloc(c->ctl_bytes, &c->ctl_off)) return PD_ERR_BUDGET;
   char* p = c->arena.ptr(c->ctl_off);
   c->d_vols = (Vol*)p;
-  p += align_up(sizeof(Vol) * 2 * (c->nslots + 1));
+  c->d_slots = (int*)(p + c->off_slots);
+  c->d_ranges = (Range*)(p + c->off_ranges);
+  p += align_up(step_block);
   c->d_ctl = (Ctl*)p;
-  p += align_up(sizeof(Ctl) * (c->nslots + 1));
-  c->d_slots = (int*)p;
-  p += align_up(sizeof(int) * c->nslots);
-  c->d_ranges = (Range*)p;
-  p += align_up(sizeof(Range) * c->range_cap);
+  c->d_abort = (int*)(p + c->off_abort);
+  p += align_up(c->off_abort + sizeof(int));
   c->d_counters = (unsigned*)p;
-  p += align_up(counter_bytes(kMaxTeamSlots));
-  c->d_abort = (int*)p;
 
   if (cfg->stream) {
     c->stream = (hipStream_t)cfg->stream;
@@ -1465,34 +1523,27 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return PD_ERR_HIP;
     c->own_stream = true;
   }
-  if (hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl) * (c->nslots + 1), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_slots, sizeof(int) * c->nslots, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * c->range_cap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&c->h_abort, sizeof(int), hipHostMallocDefault) != hipSuccess) {
-    if (c->h_vols) (void)hipHostFree(c->h_vols);
-    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
-    if (c->h_slots) (void)hipHostFree(c->h_slots);
-    if (c->h_ranges) (void)hipHostFree(c->h_ranges);
-    if (c->h_abort) (void)hipHostFree(c->h_abort);
-    if (c->own_stream) (void)hipStreamDestroy(c->stream);
-    return PD_ERR_HIP;
+  bool ok = hipHostMalloc((void**)&c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc((void**)&c->h_ctl, c->off_abort + sizeof(int), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&c->h_ranges, sizeof(Range) * c->range_cap, hipHostMallocDefault) == hipSuccess;
+  for (int s = 0; ok && s < kRunAhead; ++s)
+    ok = hipHostMalloc((void**)&c->h_stage[s], step_block, hipHostMallocDefault) == hipSuccess;
+  if (ok) {
+    c->h_abort = (int*)((char*)c->h_ctl + c->off_abort);
+    *c->h_abort = 0;
+    std::memset(c->h_vols, 0, sizeof(Vol) * 2 * (c->nslots + 1));
+    std::memset(c->h_ctl, 0, sizeof(Ctl) * (c->nslots + 1));
+    for (int s = 0; s < kRunAhead; ++s) std::memset(c->h_stage[s], 0, step_block);
+    for (int s = c->nslots - 1; s >= 0; --s) c->free_slots.push_back(s);
+    // all descriptors start idle (iters = 0)
+    ok = hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipMemcpyHostToDevice,
+                        c->stream) == hipSuccess &&
+         launch_zero(c->d_ctl, align_up(c->off_abort + sizeof(int)), c->stream) == hipSuccess &&
+         hipStreamSynchronize(c->stream) == hipSuccess;
   }
-  *c->h_abort = 0;
-  std::memset(c->h_vols, 0, sizeof(Vol) * 2 * (c->nslots + 1));
-  std::memset(c->h_ctl, 0, sizeof(Ctl) * (c->nslots + 1));
-  for (int s = c->nslots - 1; s >= 0; --s) c->free_slots.push_back(s);
-  // all descriptors start idle (iters = 0)
-  if (hipMemcpyAsync(c->d_vols, c->h_vols, sizeof(Vol) * 2 * (c->nslots + 1), hipMemcpyHostToDevice, c->stream) !=
-          hipSuccess ||
-      launch_zero(c->d_ctl, sizeof(Ctl) * (c->nslots + 1), c->stream) != hipSuccess ||
-      launch_zero(c->d_abort, align_up(sizeof(int)), c->stream) != hipSuccess ||
-      hipStreamSynchronize(c->stream) != hipSuccess) {
-    (void)hipHostFree(c->h_vols);
-    (void)hipHostFree(c->h_ctl);
-    (void)hipHostFree(c->h_slots);
-    (void)hipHostFree(c->h_ranges);
-    (void)hipHostFree(c->h_abort);
+  if (!ok) {
+    free_host(c.get());
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     return PD_ERR_HIP;
   }
@@ -1571,11 +1622,7 @@ pd_status pd_destroy(pd_ctx* c) {
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& g : c->graphs)
     if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
-  if (c->h_vols) (void)hipHostFree(c->h_vols);
-  if (c->h_ctl) (void)hipHostFree(c->h_ctl);
-  if (c->h_slots) (void)hipHostFree(c->h_slots);
-  if (c->h_ranges) (void)hipHostFree(c->h_ranges);
-  if (c->h_abort) (void)hipHostFree(c->h_abort);
+  free_host(c);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return PD_OK;

@@ -115,9 +115,20 @@ __device__ __forceinline__ void find_work_b(const Range* __restrict__ ranges, in
   g = local - p * groups;
   pair = ranges[lo].pair0 + p;
 }
+// The dispatcher hands workgroups to the XCDs round-robin (block b to XCD
+// b mod 8), and each XCD has its own L2.  Renumbering them XCD-major gives
+// each XCD one contiguous run of logical workgroups, so neighbouring column
+// strips, which share the 128-byte lines of every [ny][nx] field, meet in the
+// same L2 instead of fetching each line once per XCD.  A bijection on
+// [0, G) for any G.
+__device__ __forceinline__ int xcd_major(int b, int G) {
+  const int per = G / 8, rem = G % 8;
+  const int x = b % 8, i = b / 8;
+  return x * per + (x < rem ? x : rem) + i;
+}
 __device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int nranges, int groups,
                                           int& slot, int& pair, int& g) {
-  find_work_b(ranges, nranges, groups, (int)blockIdx.x, slot, pair, g);
+  find_work_b(ranges, nranges, groups, xcd_major((int)blockIdx.x, (int)gridDim.x), slot, pair, g);
 }
 
 // COL_FWD / COL_INV: the column transform alone (forward / inverse, in place

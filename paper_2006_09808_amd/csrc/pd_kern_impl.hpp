@@ -138,6 +138,34 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
       if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
       if (F::template pos<QA>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)n * nx + s];
     }
+  // COL_ITER: the dual prox's operands (Yhat, F delta, D) do not depend on
+  // the transform, so they are loaded before it and their latency overlaps
+  // the FFT's LDS passes instead of following them.  Not for 768-point
+  // or Bluestein transforms: there the extra registers leave one wave per
+  // SIMD, which costs more than the overlap gains.
+  constexpr int NQB = F::template nq<QB>();
+  constexpr bool kPre = MODE == COL_ITER && NY < 768 && EXT != 2;
+  cpx<T> yv[kPre ? NQB : 1][kPre ? QB : 1], ev[kPre ? NQB : 1][kPre ? QB : 1];
+  T dv[kPre ? NQB : 1][kPre ? QB : 1];
+  if constexpr (kPre) {
+    const cpx<T>* __restrict__ yh = gmem((const cpx<T>*)V.yhat) + base + c0;
+    const cpx<T>* __restrict__ dh = gmem((const cpx<T>*)V.dhat) + base + c0;
+    const T* __restrict__ dt = gmem((const T*)V.dtab) + c0;
+#pragma unroll
+    for (int q = 0; q < NQB; ++q)
+#pragma unroll
+      for (int r = 0; r < QB; ++r) {
+        int s, n;
+        yv[q][r] = ev[q][r] = mk((T)0, (T)0);
+        dv[q][r] = (T)0;
+        if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) {
+          const size_t o = (size_t)n * nx + s;
+          yv[q][r] = yh[o];
+          ev[q][r] = dh[o];
+          dv[q][r] = dt[o];
+        }
+      }
+  }
   F::template run<-1>(a, b, lds, tw, tid, len);
   if constexpr (MODE == COL_FWD || MODE == COL_FWD_CHK) {
     // forward column transform alone, in place
@@ -196,7 +224,6 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
       const T sig = (T)V.sigma;
       const T inv1ps = (T)(1.0 / (1.0 + V.sigma));
       cpx<T>* __restrict__ yh = gmem((cpx<T>*)V.yhat) + base + c0;
-      const cpx<T>* __restrict__ dh = gmem((const cpx<T>*)V.dhat) + base + c0;
 #pragma unroll
       for (int q = 0; q < F::template nq<QB>(); ++q)
 #pragma unroll
@@ -204,8 +231,17 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
           int s, n;
           if (F::template pos<QB>(tid, q, r, s, n) && inb(s, n)) {
             size_t o = (size_t)n * nx + s;
-            T d = dtab[o];
-            cpx<T> y = yh[o], e = dh[o];
+            T d;
+            cpx<T> y, e;
+            if constexpr (kPre) {
+              d = dv[q][r];
+              y = yv[q][r];
+              e = ev[q][r];
+            } else {
+              d = dtab[o];
+              y = yh[o];
+              e = gmem((const cpx<T>*)V.dhat)[base + c0 + o];
+            }
             cpx<T> yn = mk((y.x + sig * (d * b[q][r].x - e.x)) * inv1ps,
                            (y.y + sig * (d * b[q][r].y - e.y)) * inv1ps);
             yh[o] = yn;
@@ -313,6 +349,28 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
         if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
         if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)s * len + n];
       }
+    // ROW_ITER: chi_n is loaded before the inverse transform, so its latency
+    // overlaps the FFT (not for 768-point or Bluestein transforms, as in the
+    // column kernel); c then carries chi_{n+1} for the check transform
+    constexpr bool kPre = MODE == ROW_ITER && NX < 768 && EXT != 2;
+    cpx<T> c[MODE == ROW_ITER ? F::template nq<QO>() : 1][MODE == ROW_ITER ? QO : 1];
+    if constexpr (MODE == ROW_ITER && !kPre) {
+#pragma unroll
+      for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QO; ++r) c[q][r] = mk((T)0, (T)0);
+    }
+    if constexpr (kPre) {
+      const cpx<T>* __restrict__ chi0 = gmem((const cpx<T>*)V.chi) + base;
+#pragma unroll
+      for (int q = 0; q < F::template nq<QO>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QO; ++r) {
+          int s, n;
+          c[q][r] = mk((T)0, (T)0);
+          if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) c[q][r] = chi0[(size_t)s * len + n];
+        }
+    }
     F::template run<+1>(a, b, lds, tw, tid, len);
 
     if constexpr (MODE == ROW_INV_PLANAR) {
@@ -336,13 +394,6 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
       const bool check = V.check_last && it == V.iters - 1;
       const bool last = (it == V.final_it);
       cpx<T>* __restrict__ chi = gmem((cpx<T>*)V.chi) + base;
-      cpx<T> c[F::template nq<QO>()][QO];
-      if constexpr (EXT != 0) {
-#pragma unroll
-        for (int q = 0; q < F::template nq<QO>(); ++q)
-#pragma unroll
-          for (int r = 0; r < QO; ++r) c[q][r] = mk((T)0, (T)0);
-      }
       double acc[2] = {0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < F::template nq<QO>(); ++q)
@@ -351,7 +402,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
           int s, n;
           if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) {
             size_t o = (size_t)s * len + n;
-            cpx<T> x0 = chi[o];
+            const cpx<T> x0 = kPre ? c[q][r] : chi[o];
             cpx<T> u = b[q][r];
             T vx = x0.x - tau * u.x, vy = x0.y - tau * u.y;
             T nx_ = vx - clampv(vx, -tl, tl);
