@@ -140,11 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
     }
   // COL_ITER: the dual prox's operands (Yhat, F delta, D) do not depend on
   // the transform, so they are loaded before it and their latency overlaps
-  // the FFT's LDS passes instead of following them.  Not for 768-point
-  // or Bluestein transforms: there the extra registers leave one wave per
-  // SIMD, which costs more than the overlap gains.
+  // the FFT's LDS passes instead of following them.  Not for transforms
+  // longer than 512 points or Bluestein transforms: there the extra
+  // registers leave one wave per SIMD, which costs more than the overlap
+  // gains.
   constexpr int NQB = F::template nq<QB>();
-  constexpr bool kPre = MODE == COL_ITER && NY < 768 && EXT != 2;
+  constexpr bool kPre = MODE == COL_ITER && NY <= 512 && EXT != 2;
   cpx<T> yv[kPre ? NQB : 1][kPre ? QB : 1], ev[kPre ? NQB : 1][kPre ? QB : 1];
   T dv[kPre ? NQB : 1][kPre ? QB : 1];
   if constexpr (kPre) {
@@ -350,9 +351,10 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
         if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) a[q][r] = src[(size_t)s * len + n];
       }
     // ROW_ITER: chi_n is loaded before the inverse transform, so its latency
-    // overlaps the FFT (not for 768-point or Bluestein transforms, as in the
-    // column kernel); c then carries chi_{n+1} for the check transform
-    constexpr bool kPre = MODE == ROW_ITER && NX < 768 && EXT != 2;
+    // overlaps the FFT (not for transforms longer than 512 points or
+    // Bluestein transforms, as in the column kernel); c then carries
+    // chi_{n+1} for the check transform
+    constexpr bool kPre = MODE == ROW_ITER && NX <= 512 && EXT != 2;
     cpx<T> c[MODE == ROW_ITER ? F::template nq<QO>() : 1][MODE == ROW_ITER ? QO : 1];
     if constexpr (MODE == ROW_ITER && !kPre) {
 #pragma unroll

@@ -59,7 +59,7 @@ def test_any_length_up_to_384_validates(n):
 
 
 def test_bluestein_axis_tables_are_counted_in_the_state():
-    # a 258 axis carries [768 twiddles][258 chirp][768][768] complex table entries
+    # a 258 axis carries [576 twiddles][258 chirp][576][576] complex table entries
     small = pd.validate(256, 256, 1)
     big = pd.validate(256, 258, 1)
     assert big > small

@@ -59,6 +59,9 @@ OPERATOR_SHAPES = [
     (5, 3, 2, (0.0, 1.0, 0.0), (1.0, 1.0)),          # tiny
     (383, 100, 1, (0.0, 1.0, 0.0), (1.0, 1.0)),      # longest Bluestein rows (768 transforms)
     (768, 24, 2, (0.0, 1.0, 0.0), (1.0, 1.0)),       # direct 768 plan
+    (40, 576, 2, (0.3, 0.5, 0.8), (1.0, 1.0)),       # direct 576 plan (24 x 24) along columns
+    (288, 36, 1, (0.0, 1.0, 0.0), (1.0, 1.0)),       # longest Bluestein rows on 576 transforms
+    (289, 36, 1, (0.0, 1.0, 0.0), (1.0, 1.0)),       # shortest Bluestein rows on 768 transforms
 ]
 
 
@@ -79,7 +82,8 @@ def test_forward_operator_any_size(solver, torch_mod, shape):
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("shape", [OPERATOR_SHAPES[0], OPERATOR_SHAPES[3], OPERATOR_SHAPES[6]], ids=ids)
+@pytest.mark.parametrize("shape", [OPERATOR_SHAPES[0], OPERATOR_SHAPES[3], OPERATOR_SHAPES[6], OPERATOR_SHAPES[8],
+                                   OPERATOR_SHAPES[9]], ids=ids)
 def test_forward_operator_any_size_fp64(solver64, torch_mod, shape):
     # FP64 Bluestein transforms agree with the dense FP64 DFT to rounding
     nx, ny, nz, b0, vox = shape
