@@ -122,7 +122,7 @@ typedef struct {
 
 /* One reconstruction: a volume of nz slices of ny x nx voxels (Eq. (1)). */
 typedef struct {
-  int nx, ny, nz;      /* nx, ny: 8,16,24,32,48,64,96,128,192,256,384,512,576,768
+  int nx, ny, nz;      /* nx, ny: 8,16,24,32,48,64,96,128,192,256,288,384,512,576,768
                           (direct FFT plans) or any other length 2..384, whose
                           DFTs run as Bluestein (chirp-z) convolutions on the
                           smallest direct length >= 2n - 1                      */

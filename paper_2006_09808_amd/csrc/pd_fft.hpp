@@ -244,6 +244,7 @@ PD_PLAN(96, 2, 8, 12, 1)
 PD_PLAN(128, 2, 16, 8, 1)
 PD_PLAN(192, 2, 16, 12, 1)
 PD_PLAN(256, 2, 16, 16, 1)
+PD_PLAN(288, 2, 12, 24, 1)
 PD_PLAN(384, 2, 16, 24, 1)
 PD_PLAN(512, 3, 8, 8, 8)
 PD_PLAN(576, 2, 24, 24, 1)

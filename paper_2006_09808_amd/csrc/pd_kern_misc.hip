@@ -18,6 +18,7 @@ PD_DECL(96)
 PD_DECL(128)
 PD_DECL(192)
 PD_DECL(256)
+PD_DECL(288)
 PD_DECL(384)
 PD_DECL(512)
 PD_DECL(576)
@@ -56,7 +57,7 @@ const ResidentVariant* resident_variant(int n, int v) {
 bool size_supported(int n) {
   switch (n) {
     case 8: case 16: case 24: case 32: case 48: case 64: case 96:
-    case 128: case 192: case 256: case 384: case 512: case 576: case 768:
+    case 128: case 192: case 256: case 288: case 384: case 512: case 576: case 768:
       return true;
     default:
       return false;
@@ -64,7 +65,7 @@ bool size_supported(int n) {
 }
 
 int blue_len(int n) {
-  static const int lens[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 576, 768};
+  static const int lens[] = {8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 288, 384, 512, 576, 768};
   if (n < 2) return 0;
   for (int m : lens)
     if (m >= 2 * n - 1) return m;
@@ -79,7 +80,7 @@ hipError_t launch_col(int n, int mode, int g, int grid, int groups, const Vol* v
   switch (n) {
     PD_CASE(8, col) PD_CASE(16, col) PD_CASE(24, col) PD_CASE(32, col) PD_CASE(48, col)
     PD_CASE(64, col) PD_CASE(96, col) PD_CASE(128, col) PD_CASE(192, col) PD_CASE(256, col)
-    PD_CASE(384, col) PD_CASE(512, col) PD_CASE(576, col) PD_CASE(768, col)
+    PD_CASE(288, col) PD_CASE(384, col) PD_CASE(512, col) PD_CASE(576, col) PD_CASE(768, col)
     default: return hipErrorInvalidValue;
   }
 }
@@ -89,7 +90,7 @@ hipError_t launch_row(int n, int mode, int g, int grid, int groups, const Vol* v
   switch (n) {
     PD_CASE(8, row) PD_CASE(16, row) PD_CASE(24, row) PD_CASE(32, row) PD_CASE(48, row)
     PD_CASE(64, row) PD_CASE(96, row) PD_CASE(128, row) PD_CASE(192, row) PD_CASE(256, row)
-    PD_CASE(384, row) PD_CASE(512, row) PD_CASE(576, row) PD_CASE(768, row)
+    PD_CASE(288, row) PD_CASE(384, row) PD_CASE(512, row) PD_CASE(576, row) PD_CASE(768, row)
     default: return hipErrorInvalidValue;
   }
 }

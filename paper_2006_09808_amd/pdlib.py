@@ -25,7 +25,7 @@ KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z = 0, 1
 
 # lengths with a direct FFT plan; any other length 2..MAX_BLUESTEIN runs
 # through the Bluestein (chirp-z) engine
-SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 576, 768)
+SUPPORTED_SIZES = (8, 16, 24, 32, 48, 64, 96, 128, 192, 256, 288, 384, 512, 576, 768)
 MAX_BLUESTEIN = 384
 
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",

@@ -62,6 +62,9 @@ OPERATOR_SHAPES = [
     (40, 576, 2, (0.3, 0.5, 0.8), (1.0, 1.0)),       # direct 576 plan (24 x 24) along columns
     (288, 36, 1, (0.0, 1.0, 0.0), (1.0, 1.0)),       # longest Bluestein rows on 576 transforms
     (289, 36, 1, (0.0, 1.0, 0.0), (1.0, 1.0)),       # shortest Bluestein rows on 768 transforms
+    (288, 48, 2, (0.0, 1.0, 0.0), (1.0, 1.0)),       # direct 288 plan (12 x 24)
+    (48, 144, 1, (1.0, 0.0, 1.0), (1.0, 1.0)),       # longest Bluestein columns on 288 transforms
+    (48, 145, 1, (1.0, 0.0, 1.0), (1.0, 1.0)),       # shortest Bluestein columns on 384 transforms
 ]
 
 
