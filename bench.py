@@ -173,9 +173,10 @@ def _device_delta(s, w, dev):
 
 
 def other_workloads(reps=20):
-    """The single-slice latency case, the uneven batch and a stack of 256
+    """The single-slice latency case, the uneven batch, a stack of 256
     slices (its state, 96 MiB, no longer fits the 256 MiB last-level cache
-    together with the exchange buffers), each on a fresh context."""
+    together with the exchange buffers), the paper's 256x258 stack and the
+    FP32/FP64 precision workload, each on a fresh context."""
     import torch
     import pd_inputs
     import paper_2006_09808_amd as pd
@@ -249,6 +250,34 @@ def other_workloads(reps=20):
                 best = dt if best is None else min(best, dt)
         out["paper_shape_256x258x25_500it"] = {"ms": best * 1e3,
                                                "voxel_iterations_per_s": 25 * 256 * 258 * ITERS / best}
+    # precision workload: 128 slices of 256x256 with a tilted needle, 0.5%
+    # noise, lambda 5e-4, 800 iterations, FP32 and FP64 (the same kernels in
+    # double) on the GPU; agreement of the two in relative L2 and ppm
+    w = pd_inputs.config4()
+    res = {}
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        delta4 = _device_delta(s, w, dev).cpu().numpy()      # one FP32 field map for both runs
+    for prec, dt_np in (("fp32", np.float32), ("fp64", np.float64)):
+        with pd.Solver(arena_bytes=8 << 30, device=0, precision=prec) as s:
+            if prec == "fp32":
+                s.tune(256, 256, 128, iters=20)
+            d = torch.from_numpy(delta4.astype(dt_np)).to(dev)
+            chi = torch.empty_like(d)
+            sp = w.solver_params()
+            best = None
+            for _ in range(2):
+                t0 = pd.now()
+                r = s.poll(s.submit([(d, chi, sp)])[0], -1)
+                if r["status"] != pd.PD_OK:
+                    raise RuntimeError("precision workload solve failed")
+                dt = pd.now() - t0
+                best = dt if best is None else min(best, dt)
+            res[prec] = (chi.cpu().numpy().astype(np.float64), best)
+    c32, c64 = res["fp32"][0], res["fp64"][0]
+    out["precision_256x256x128_800it"] = {
+        "fp32_ms": res["fp32"][1] * 1e3, "fp64_ms": res["fp64"][1] * 1e3,
+        "relL2_fp32_vs_fp64": float(np.linalg.norm(c32 - c64) / np.linalg.norm(c64)),
+        "max_abs_ppm_fp32_vs_fp64": float(np.abs(c32 - c64).max())}
     return out
 
 
@@ -357,12 +386,25 @@ def cpu_baseline(w, nslices, iters):
     field = oracle.forward(chi)
     delta = pd_inputs.make_delta(field, w.eta[:nslices], w.rho).astype(np.float32).astype(np.float64)
     t0 = time.perf_counter()
-    oracle.solve(delta, lam=w.lam, tau=w.tau, sigma=w.sigma, theta=w.theta, max_iter=iters)
+    ref, _ = oracle.solve(delta, lam=w.lam, tau=w.tau, sigma=w.sigma, theta=w.theta, max_iter=iters)
     dt = time.perf_counter() - t0
     vit = nslices * NX * NY * iters
-    return {"value": vit / dt, "unit": "voxel-iterations/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d of %d slices (256x256), %d of %d iterations, FP64 dense-DFT oracle, %.1f s"
-                      % (nslices, NZ, iters, ITERS, dt)}
+    out = {"value": vit / dt, "unit": "voxel-iterations/s", "cores": int(threads), "kind": "oracle",
+           "sample": "%d of %d slices (256x256), %d of %d iterations, FP64 dense-DFT oracle, %.1f s"
+                     % (nslices, NZ, iters, ITERS, dt)}
+    # the same sample solved on the GPU (FP32, the autotuned launch
+    # configuration of the bench shape), against the oracle's iterate
+    import torch
+    import paper_2006_09808_amd as pd
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        s.tune(NX, NY, nslices, iters=50)
+        got, info = s.solve(torch.from_numpy(delta.astype(np.float32)).to("cuda:0"), lam=w.lam, tau=w.tau,
+                            sigma=w.sigma, theta=w.theta, max_iter=iters)
+    got = got.cpu().numpy().astype(np.float64)
+    out["parity"] = {"relL2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+                     "max_abs_ppm": float(np.abs(got - ref).max()), "tolerance": 1e-4,
+                     "gpu": "FP32, %d iterations" % info["iterations"]}
+    return out
 
 
 def main():
