@@ -238,6 +238,41 @@ def test_batch_results_equal_solo_results(solver, torch_mod):
         np.testing.assert_array_equal(chi.cpu().numpy().astype(np.float64), sgot)
 
 
+def test_staggered_gap_stops_in_one_batch_equal_solo_runs(solver, torch_mod):
+    """Volumes whose gap reaches the tolerance at different checks share the
+    scheduler's rounds of several steps with a volume that runs to its cap:
+    launches after a mid-round stop skip the stopped volume, so every result,
+    iteration count and gap equals the volume's solo run."""
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    rng = np.random.default_rng(401)
+    cases = []
+    for ts, lam in ((0.3, 0.3), (0.2, 0.05), (0.1, 0.3)):     # identity kernel: stops near 70, 120, 190
+        d = rng.normal(size=(2, 32, 48)).astype(np.float32)
+        cases.append((d, dict(lam=lam, tau=ts, sigma=ts, theta=1.0, max_iter=400, gap_tol=1e-5, check_every=5,
+                              kernel="identity")))
+    w, d = make_case(402, 3, 64, 64, max_iter=150, gap_tol=1e-5, check_every=5)
+    cases.append((d, w.solver_params()))
+    _say("staggered gap stops: 3 identity volumes + 1 dipole volume capped at 150")
+    jobs = []
+    for d, sp in cases:
+        dt = torch.from_numpy(d).to("cuda:0")
+        jobs.append((dt, torch.empty_like(dt), sp))
+    infos = [solver.poll(t, -1) for t in solver.submit(jobs)]
+    its = [i["iterations"] for i in infos]
+    _say("  iterations %s" % (its,))
+    assert all(i["status"] == pd.PD_OK for i in infos)
+    assert its[3] == 150
+    assert len(set(its[:3])) == 3 and max(its[:3]) < 400
+    for (dt, chi, sp), info in zip(jobs, infos):
+        solo = torch.empty_like(dt)
+        (t,) = solver.submit([(dt, solo, sp)])
+        sinfo = solver.poll(t, -1)
+        assert sinfo["iterations"] == info["iterations"]
+        assert sinfo["rel_gap"] == info["rel_gap"]
+        np.testing.assert_array_equal(solo.cpu().numpy(), chi.cpu().numpy())
+
+
 def test_deterministic_bitwise(solver, torch_mod):
     w, delta = make_case(41, 4, 128, 64, max_iter=30)
     a, _ = gpu_solve(solver, torch_mod, delta, **w.solver_params())
