@@ -80,3 +80,50 @@ def test_admission_waits_for_arena(torch_mod):
         ref, _ = oracle.solve(d.astype(np.float64), **w.solver_params())
         err = np.linalg.norm(r.chi.cpu().numpy() - ref) / np.linalg.norm(ref)
         assert err <= 1e-4
+
+
+def test_serving_mix_sampled_against_oracle_and_under_a_small_arena(torch_mod):
+    """The serving workload's request mix (Poisson arrivals at 20/s, 128^2 to
+    384^2, 16-64 slices, tolerance 1e-5) on a short schedule with a 300-
+    iteration cap (so the oracle check stays affordable): every 8th request's
+    first slice against the oracle at the request's iteration count (slices
+    are independent at a fixed count), and the same schedule again under a
+    512 MiB arena (admission waits, shorter steps) with bitwise equal results."""
+    import paper_2006_09808_amd as pd
+    from paper_2006_09808_amd import serve
+    torch = torch_mod
+    sched = pd_inputs.serving_schedule(seed=5100, rate=20.0, duration=1.5)
+    base = {}
+    for i, n in enumerate(pd_inputs.SERVING_SIZES):
+        w = pd_inputs.serving_request(5200 + i, n, 64)
+        base[n] = pd_inputs.make_delta(oracle.forward(w.chi_true), w.eta, w.rho).astype(np.float32)
+    params = dict(lam=1e-3, tau=1.4, sigma=1.4, theta=1.0, max_iter=300, gap_tol=1e-5, check_every=10)
+
+    def run(arena):
+        with pd.Solver(arena_bytes=arena, device=0) as s:
+            reqs = []
+            for (t, n, nz, seed) in sched:
+                off = seed % (64 - nz + 1)
+                d = torch.from_numpy(np.ascontiguousarray(base[n][off:off + nz])).to("cuda:0")
+                reqs.append(serve.Request(t, d, torch.empty_like(d), params))
+            summary = serve.run_open_loop(s, reqs)
+        return reqs, summary
+
+    big, sb = run(16 << 30)
+    _say("serving mix: %d requests, p50 %.1f ms p99 %.1f ms" % (len(big), sb["p50_s"] * 1e3, sb["p99_s"] * 1e3))
+    assert sb["ok"] == len(big) >= 10
+    small, ss = run(512 << 20)
+    _say("under 512 MiB: p50 %.1f ms p99 %.1f ms" % (ss["p50_s"] * 1e3, ss["p99_s"] * 1e3))
+    assert ss["ok"] == len(small)
+    for a, b in zip(big, small):
+        assert a.result["iterations"] == b.result["iterations"]
+        assert a.result["rel_gap"] == b.result["rel_gap"]
+        np.testing.assert_array_equal(a.chi.cpu().numpy(), b.chi.cpu().numpy())
+    for r in big[::8]:
+        d = r.delta[0:1].cpu().numpy().astype(np.float64)
+        ref, _ = oracle.solve(d, **dict(params, gap_tol=0.0, max_iter=r.result["iterations"]))
+        got = r.chi[0:1].cpu().numpy().astype(np.float64)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        _say("  request %dx%dx%d, %d iterations: slice 0 relL2 %.3e" % (
+            r.delta.shape[2], r.delta.shape[1], r.delta.shape[0], r.result["iterations"], err))
+        assert err <= 1e-4
