@@ -215,7 +215,8 @@ def other_workloads(reps=20):
         vit = sum(int(j[0].numel()) * i["iterations"] for j, i in zip(jobs, infos))
         out["uneven_128x32_256x48_384x24_1e-5"] = {
             "wall_ms": min(walls) * 1e3, "iterations": [i["iterations"] for i in infos],
-            "rel_gap": [i["rel_gap"] for i in infos], "voxel_iterations_per_s": vit / min(walls)}
+            "rel_gap": [i["rel_gap"] for i in infos], "voxel_iterations_per_s": vit / min(walls),
+            "cap_hit": [i["iterations"] >= j[2]["max_iter"] for j, i in zip(jobs, infos)]}
     w = pd_inputs.random_stack(2500, 256, NY, NX, lam=1e-3, max_iter=ITERS)
     with pd.Solver(arena_bytes=4 << 30, device=0) as s:
         d = _device_delta(s, w, dev)
@@ -461,7 +462,9 @@ def main():
               (("column", pd.KIND_COLUMN), ("row", pd.KIND_ROW), ("resident", pd.KIND_RESIDENT))}
 
     per_slice = None
+    per_slice_rel = None
     if not a.no_per_slice:
+        chi_batched = chi.clone()
         # plain per-slice GPU loop: each slice solved alone, one after another,
         # two kernel launches per iteration (the paper's slice loop on the GPU)
         with pd.Solver(arena_bytes=1 << 30, device=0, resident=False) as s1:
@@ -477,6 +480,10 @@ def main():
             slice_pass()
             torch.cuda.synchronize()
             per_slice = time.perf_counter() - t1
+        # same iterates up to rounding (a slice alone rides with a zero
+        # partner instead of its neighbour)
+        per_slice_rel = float(torch.linalg.vector_norm((chi - chi_batched).double()) /
+                              torch.linalg.vector_norm(chi_batched.double()))
 
     vit = NZ * NX * NY * ITERS
     value = vit * a.steps / dt
@@ -528,7 +535,7 @@ def main():
                    "slices": NZ, "nx": NX, "ny": NY, "iterations": ITERS, "parallelism": "single GPU"},
         "per_slice": None if per_slice is None else {
             "value": vit / per_slice, "unit": "voxel-iterations/s", "ms_per_solve": per_slice * 1e3,
-            "speedup_batched": value / (vit / per_slice)},
+            "speedup_batched": value / (vit / per_slice), "relL2_vs_batched": per_slice_rel},
         "roofline": roofline,
         "rel_gap": info["rel_gap"],
         "autotune": {"choice": tune_choice, "timings": tune_table},
