@@ -405,6 +405,17 @@ def cpu_baseline(w, nslices, iters):
     out["parity"] = {"relL2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
                      "max_abs_ppm": float(np.abs(got - ref).max()), "tolerance": 1e-4,
                      "gpu": "FP32, %d iterations" % info["iterations"]}
+    # the single 64x64 slice workload in full (200 iterations): small enough
+    # for the oracle, so its GPU result is checked whole
+    w1 = pd_inputs.config1()
+    d1 = pd_inputs.make_delta(oracle.forward(w1.chi_true), w1.eta, w1.rho).astype(np.float32)
+    ref1, _ = oracle.solve(d1.astype(np.float64), **w1.solver_params())
+    with pd.Solver(arena_bytes=256 << 20, device=0) as s:
+        got1, info1 = s.solve(torch.from_numpy(d1).to("cuda:0"), **w1.solver_params())
+    got1 = got1.cpu().numpy().astype(np.float64)
+    out["parity_single_64x64x1_200it"] = {
+        "relL2": float(np.linalg.norm(got1 - ref1) / np.linalg.norm(ref1)),
+        "max_abs_ppm": float(np.abs(got1 - ref1).max()), "tolerance": 1e-4, "iterations": info1["iterations"]}
     return out
 
 
