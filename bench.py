@@ -87,8 +87,9 @@ KERNEL_SOURCES = {
     "tv_row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_tv_row.hpp"),
 }
 # FP32 vector ALU ceilings of MI355X.  Published: 157.3 TFLOP/s, which needs
-# packed FP32 (two FMAs per lane per instruction).  This build emits no packed
-# FP32, so the ceiling of its kernels, from the unit counts and the clock, is
+# packed FP32 (two FMAs per lane per instruction).  The library is compiled
+# without packed FP32, so the ceiling of its kernels, from the unit counts and
+# the clock, is
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (one FMA) x 2.4 GHz = 78.6 TFLOP/s:
 # the roofline's peak.
 FP32_PEAK_TFLOPS = 157.3
