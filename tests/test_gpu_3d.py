@@ -53,6 +53,7 @@ SHAPES = [
     (48, 32, 12, (0.3, 0.5, 0.8), (0.8, 1.2), 1.5),     # oblique B0, anisotropic
     (43, 20, 7, (1.0, 1.0, 1.0), (1.0, 1.0), 1.0),      # Bluestein along x and z, odd nz
     (256, 256, 8, (0.0, 1.0, 0.0), (1.0, 1.0), 2.0),
+    (16, 12, 140, (0.2, 0.4, 0.9), (1.0, 1.0), 0.5),   # Bluestein z on 288 transforms, partial strips
 ]
 
 

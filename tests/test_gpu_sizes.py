@@ -86,7 +86,7 @@ def test_forward_operator_any_size(solver, torch_mod, shape):
 
 
 @pytest.mark.parametrize("shape", [OPERATOR_SHAPES[0], OPERATOR_SHAPES[3], OPERATOR_SHAPES[6], OPERATOR_SHAPES[8],
-                                   OPERATOR_SHAPES[9]], ids=ids)
+                                   OPERATOR_SHAPES[9], OPERATOR_SHAPES[12]], ids=ids)
 def test_forward_operator_any_size_fp64(solver64, torch_mod, shape):
     # FP64 Bluestein transforms agree with the dense FP64 DFT to rounding
     nx, ny, nz, b0, vox = shape
