@@ -27,6 +27,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <thread>
 #include <vector>
@@ -881,6 +883,13 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
   return hipStreamSynchronize(c->stream);
 }
 
+// A failed HIP call of a step, named on stderr when PD_DEBUG is set
+// (diagnostics only: the request's status reports PD_ERR_HIP).
+inline hipError_t step_err(const char* what, hipError_t e) {
+  if (e != hipSuccess && std::getenv("PD_DEBUG")) std::fprintf(stderr, "pd: %s: %s\n", what, hipGetErrorName(e));
+  return e;
+}
+
 // HIP events of timed launches, read back after a round
 struct StepEvents {
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> evs;
@@ -1117,7 +1126,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
                           c->stream);
     });
-    if (e != hipSuccess) return e;
+    if (step_err("resident launch", e) != hipSuccess) return e;
   }
   // two-launch path (K iterations of column and row launches), then the
   // checks: replayed from a captured graph when the same plan recurs
@@ -1256,12 +1265,12 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       }
     }
     if (G.exec) {
-      if ((e = hipGraphLaunch(G.exec, c->stream)) != hipSuccess) return e;
+      if ((e = step_err("graph launch", hipGraphLaunch(G.exec, c->stream))) != hipSuccess) return e;
       c->graph_replays++;
-    } else if ((e = enqueue_rest(false)) != hipSuccess) {
+    } else if ((e = step_err("two-launch kernels", enqueue_rest(false))) != hipSuccess) {
       return e;
     }
-  } else if ((e = enqueue_rest(c->time_kernels)) != hipSuccess) {
+  } else if ((e = step_err("two-launch kernels", enqueue_rest(c->time_kernels))) != hipSuccess) {
     return e;
   }
   return hipSuccess;
@@ -1299,8 +1308,8 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
       c->ev_pool.push_back(x.second.second);
     }
   }
-  if (e != hipSuccess) return e;
-  if (*c->h_abort) return hipErrorLaunchTimeOut;   // a team barrier gave up
+  if (step_err("round", e) != hipSuccess) return e;
+  if (*c->h_abort) return step_err("team barrier", hipErrorLaunchTimeOut);   // a team barrier gave up
   return hipSuccess;
 }
 
