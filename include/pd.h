@@ -192,8 +192,10 @@ pd_status pd_destroy(pd_ctx* c);
 const char* pd_status_string(pd_status s);
 
 /* Pure host check of one request, no GPU involved: the same validation
- * pd_solve_batch applies (except the arena size).  If state_bytes is non-null
- * it receives the arena bytes the request occupies while resident. */
+ * pd_solve_batch applies, except the arena size and the device pointers
+ * (delta, chi, weight, mask may still be null, so a caller can size its
+ * allocations first).  If state_bytes is non-null it receives the arena
+ * bytes the request occupies while resident. */
 pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes);
 
 /* Largest |D(k)| of the request's kernel grid (||A||_2), computed in FP64 on

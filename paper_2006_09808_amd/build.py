@@ -19,6 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build", "hip")
 LIB = os.path.join(PKG, "libpd_hip.so")
+EXAMPLE = os.path.join(PKG, "examples", "pd_solve_file")
 
 ARCH = "gfx950"
 CXXFLAGS = [
@@ -78,6 +79,13 @@ def build(jobs=None, verbose=False):
     if p.returncode != 0:
         raise RuntimeError("link failed:\n" + p.stdout)
     os.replace(tmp, LIB)
+    # the C-ABI example program, linked against the library just built
+    ex_src = os.path.join(PKG, "examples", "pd_solve_file.cpp")
+    if os.path.exists(ex_src):
+        cmd = [cc] + CXXFLAGS + [ex_src, "-o", EXAMPLE, "-L" + PKG, "-l:libpd_hip.so", "-Wl,-rpath,$ORIGIN/.."]
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        if p.returncode != 0:
+            raise RuntimeError("example build failed:\n" + p.stdout)
     if verbose:
         print("built %s from %d units in %.1f s" % (LIB, len(srcs), time.time() - t0), file=sys.stderr)
     return LIB

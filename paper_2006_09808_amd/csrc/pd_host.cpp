@@ -367,7 +367,9 @@ double cached_kernel_norm(const pd_request* r) {
   return L;
 }
 
-pd_status validate(const pd_request* r, int precision, double* norm_out) {
+// check_ptrs: the device arrays must be given (a solve); pd_validate sizes a
+// request before they exist and skips that test.
+pd_status validate(const pd_request* r, int precision, double* norm_out, bool check_ptrs = true) {
   if (!r) return PD_ERR_ARG;
   if (precision != PD_FP32 && precision != PD_FP64) return PD_ERR_ARG;
   if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
@@ -378,12 +380,12 @@ pd_status validate(const pd_request* r, int precision, double* norm_out) {
   if (r->max_iter < 0) return PD_ERR_ARG;
   if (!isfin(r->gap_tol) || r->gap_tol < 0) return PD_ERR_ARG;
   if (r->gap_tol > 0 && r->check_every < 1) return PD_ERR_ARG;
-  if (!r->delta || !r->chi) return PD_ERR_ARG;
+  if (check_ptrs && (!r->delta || !r->chi)) return PD_ERR_ARG;
   if (r->model != PD_MODEL_L1 && r->model != PD_MODEL_TV) return PD_ERR_ARG;
   if (r->model == PD_MODEL_TV) {
     // lam weights the data term (it divides sigma in the dual prox); the
     // model runs a fixed number of iterations
-    if (!r->weight || !r->mask || r->gap_tol != 0.0 || !(r->lambda > 0)) return PD_ERR_ARG;
+    if ((check_ptrs && (!r->weight || !r->mask)) || r->gap_tol != 0.0 || !(r->lambda > 0)) return PD_ERR_ARG;
   }
   if (!isfin(r->tau) || !isfin(r->sigma) || r->tau <= 0 || r->sigma <= 0) return PD_ERR_STEP;
   if (!isfin(r->theta) || r->theta < 0 || r->theta > 1) return PD_ERR_STEP;
@@ -1465,7 +1467,7 @@ const char* pd_status_string(pd_status s) {
 double pd_now(void) { return now_s(); }
 
 pd_status pd_validate(const pd_request* r, int precision, size_t* state_bytes) {
-  pd_status s = validate(r, precision, nullptr);
+  pd_status s = validate(r, precision, nullptr, false);
   if (s != PD_OK) return s;
   if (state_bytes) *state_bytes = layout_of(*r, precision).total + table_bytes(r->nx, r->ny, nz3_of(*r), precision);
   return PD_OK;
