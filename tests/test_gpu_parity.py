@@ -145,6 +145,26 @@ def test_fixed_iterations_match_oracle(request, torch_mod, path, seed, nz, ny, n
     assert info["primal"] == pytest.approx(iref["primal"], rel=1e-4)
 
 
+@pytest.mark.parametrize("path", ["default", "two_launch"])
+@pytest.mark.parametrize("iters", [1, 2, 10])
+@pytest.mark.parametrize("nz,ny,nx", [(2, 64, 64), (3, 256, 256), (3, 96, 64)])
+def test_first_iterations_match_oracle(request, torch_mod, path, iters, nz, ny, nx):
+    """The first iterates, where the over-relaxed point and the dual start
+    from zero, with a gap check after every iteration (tolerance never met)."""
+    solver = request.getfixturevalue({"default": "solver", "two_launch": "solver_two"}[path])
+    w, delta = make_case(600 + nx + iters, nz, ny, nx, lam=1e-3, max_iter=iters, gap_tol=1e-14, check_every=1)
+    sp = w.solver_params()
+    got, info = gpu_solve(solver, torch_mod, delta, **sp)
+    ref, iref = oracle.solve(delta.astype(np.float64), **sp)
+    err = rel_l2(got, ref)
+    _say("[%s] %dx%dx%d after %d: relL2 %.3e gap %.6e (oracle %.6e)" % (path, nx, ny, nz, iters, err,
+                                                                      info["rel_gap"], iref["rel_gap"]))
+    assert info["iterations"] == iref["iterations"] == iters
+    assert err <= REL_TOL
+    assert info["rel_gap"] == pytest.approx(iref["rel_gap"], rel=1e-4)
+    assert info["primal"] == pytest.approx(iref["primal"], rel=1e-5)
+
+
 def test_config1_plain_64x64(solver, torch_mod):
     w = pd_inputs.config1()
     field = oracle.forward(w.chi_true)
