@@ -79,12 +79,13 @@ def copy_probe(nbytes, reps=5):
 
 
 KERNEL_SOURCES = {
-    # the profile summaries hash the kernel sources they were taken with
-    "column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp"),
-    "row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp"),
-    "resident": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_resident.hpp"),
-    "tv_column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp"),
-    "tv_row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_tv_row.hpp"),
+    # the profile summaries hash the kernel sources they were taken with, and
+    # the build script that holds the compiler flags
+    "column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "../build.py"),
+    "row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "../build.py"),
+    "resident": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_resident.hpp", "../build.py"),
+    "tv_column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "../build.py"),
+    "tv_row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_tv_row.hpp", "../build.py"),
 }
 # FP32 vector ALU ceilings of MI355X.  Published: 157.3 TFLOP/s, which needs
 # packed FP32 (two FMAs per lane per instruction).  The library is compiled

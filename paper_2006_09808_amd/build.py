@@ -26,6 +26,10 @@ CXXFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
     # packed FP32 instructions are kept out of all generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a*b+c fuses into an FMA only within one source expression, so the
+    # rounding of every update is fixed by the source and not by how the
+    # compiler unrolls or schedules a particular tile or team shape
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wall", "-Wno-unused-function",
 ]
