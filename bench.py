@@ -186,6 +186,7 @@ def other_workloads(reps=20):
     out = {}
     w = pd_inputs.config1()
     with pd.Solver(arena_bytes=256 << 20, device=0) as s:
+        s.tune(64, 64, 1, iters=50)          # the latency case's own launch configuration
         d = _device_delta(s, w, dev)
         chi = torch.empty_like(d)
         sp = w.solver_params()
