@@ -242,7 +242,9 @@ typedef struct {
  * variants for square FP32 shapes; row/column tile sizes of the two-launch
  * kernels), then make the fastest of each path the context's choice for that
  * shape.  Needs arena space like a solve of that size; blocks until done and
- * runs between scheduling steps.  Up to max_entries timings are written to
+ * runs between scheduling rounds.  The choice is per shape, whatever the
+ * slice count of later requests: the widest resident teams win for small
+ * batches and lose for large ones, so tune with a representative nz.  Up to max_entries timings are written to
  * entries (may be NULL), their count to *n_entries.
  * Errors: PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_BUDGET, PD_ERR_HIP. */
 pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
