@@ -991,8 +991,25 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
         (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv &&
          !z3)
             ? resident_variant(nx, tn.res_variant) : nullptr;
+    int maxt = rv ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
+    if (rv) {
+      // the chosen variant was timed at some slice count; when this step's
+      // pairs need more than one of its co-resident launches, take the
+      // variant with the most co-resident teams instead (all variants give
+      // the same bits)
+      int npairs = 0;
+      for (Job* j : g.second) npairs += j->L.P;
+      if (npairs > maxt)
+        for (int v = 0; v < resident_variant_count(nx); ++v) {
+          const ResidentVariant* cand = resident_variant(nx, v);
+          const int m = std::min(cand->max_teams(), kMaxTeamSlots);
+          if (m > maxt) {
+            rv = cand;
+            maxt = m;
+          }
+        }
+    }
     int team = rv ? rv->team() : 0;
-    int maxt = team ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
     if (team && maxt > 0) {
       // split the shape's pairs into co-resident batches
       Launch L{};
