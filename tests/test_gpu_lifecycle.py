@@ -1,0 +1,98 @@
+"""Context lifecycle and host concurrency through the C ABI: submissions and
+polls from several host threads at once give each request its solo result,
+and destroying a context with requests still queued or running returns
+promptly and leaves the device usable."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import pd_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(seed, nz, ny, nx, iters):
+    w = pd_inputs.random_stack(seed, nz, ny, nx, lam=1e-3, max_iter=iters)
+    return w, pd_inputs.make_delta(oracle.forward(w.chi_true), w.eta, w.rho).astype(np.float32)
+
+
+def test_concurrent_submitters_get_their_solo_results(torch_mod):
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    shapes = [(3, 64, 64, 40), (2, 128, 128, 30), (4, 96, 64, 35), (1, 256, 256, 25)]
+    cases = [_case(700 + i, *sh) for i, sh in enumerate(shapes)]
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        solo = []
+        for w, d in cases:
+            chi, info = s.solve(torch.from_numpy(d).to("cuda:0"), **w.solver_params())
+            solo.append((chi.cpu().numpy(), info["iterations"]))
+        results = {}
+        errors = []
+
+        def worker(k):
+            try:
+                for rep in range(3):
+                    for i in range(len(cases)):
+                        w, d = cases[(i + k) % len(cases)]
+                        dt = torch.from_numpy(d).to("cuda:0")
+                        out = torch.empty_like(dt)
+                        (t,) = s.submit([(dt, out, w.solver_params())])
+                        info = s.poll(t, -1)
+                        results[(k, rep, (i + k) % len(cases))] = (out.cpu().numpy(), info)
+            except Exception as e:          # reported below, in the test's thread
+                errors.append(repr(e))
+
+        threads = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=120)
+        assert not any(th.is_alive() for th in threads)
+    assert not errors, errors
+    assert len(results) == 4 * 3 * len(cases)
+    for (k, rep, i), (chi, info) in results.items():
+        assert info["status"] == pd.PD_OK and info["iterations"] == solo[i][1]
+        np.testing.assert_array_equal(chi, solo[i][0])
+    _say("%d solves from 4 threads equal their solo runs" % len(results))
+
+
+def test_destroy_with_requests_in_flight(torch_mod):
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    w, d = _case(720, 64, 256, 256, 5000)
+    s = pd.Solver(arena_bytes=1 << 30, device=0)
+    dt = torch.from_numpy(d).to("cuda:0")
+    outs = [torch.empty_like(dt) for _ in range(3)]
+    tickets = s.submit([(dt, o, w.solver_params()) for o in outs])     # more than one fits: some queue
+    time.sleep(0.02)
+    _, resident, queued = s.arena_usage()
+    _say("in flight at destroy: %d resident, %d queued" % (resident, queued))
+    assert resident + queued >= 1
+    t0 = time.perf_counter()
+    s.close()
+    dt_close = time.perf_counter() - t0
+    _say("destroy took %.1f ms" % (dt_close * 1e3))
+    assert dt_close < 5.0
+    assert len(tickets) == 3
+    # the device and the library are still usable
+    w2, d2 = _case(721, 2, 64, 64, 20)
+    with pd.Solver(arena_bytes=256 << 20, device=0) as s2:
+        chi, info = s2.solve(torch.from_numpy(d2).to("cuda:0"), **w2.solver_params())
+    ref, _ = oracle.solve(d2.astype(np.float64), **w2.solver_params())
+    assert info["status"] == pd.PD_OK
+    assert np.linalg.norm(chi.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-4
