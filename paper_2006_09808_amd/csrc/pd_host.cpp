@@ -15,6 +15,7 @@
 //   volume keeps its primal, dual and exchange state in the arena between
 //   steps (the paper's device residency, Sec. II-D).
 #include "pd.h"
+#include "pd_arena.hpp"
 #include "pd_internal.hpp"
 
 #include <algorithm>
@@ -34,6 +35,7 @@
 #include <vector>
 
 using namespace pdk;
+using pdh::Arena;
 
 namespace {
 
@@ -396,59 +398,6 @@ pd_status validate(const pd_request* r, int precision, double* norm_out, bool ch
   if (norm_out) *norm_out = L;
   return PD_OK;
 }
-
-// ---------------------------------------------------------------------------
-// first-fit arena allocator over the caller's device memory
-// ---------------------------------------------------------------------------
-class Arena {
- public:
-  void init(char* base, size_t size) {
-    base_ = base;
-    size_ = size;
-    free_.clear();
-    if (size) free_[0] = size;
-    used_ = 0;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = align_up(std::max<size_t>(bytes, 1));
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        size_t o = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[o + bytes] = len - bytes;
-        used_ += bytes;
-        *off = o;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = align_up(std::max<size_t>(bytes, 1));
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  char* ptr(size_t off) const { return base_ + off; }
-  size_t used() const { return used_; }
-  size_t size() const { return size_; }
-
- private:
-  char* base_ = nullptr;
-  size_t size_ = 0, used_ = 0;
-  std::map<size_t, size_t> free_;
-};
 
 // per kernel shape: D grid and the twiddles of both axes, in the arena
 struct TableKey {
