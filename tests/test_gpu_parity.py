@@ -121,6 +121,8 @@ SOLVE_CASES = [
     (7, 3, 256, 256, dict(lam=1e-3, max_iter=40)),
     (8, 5, 64, 64, dict(lam=1e-3, max_iter=45, b0=(0.6, 0.8, 0.0), theta=0.7)),
     (9, 3, 192, 192, dict(lam=1e-3, max_iter=50)),
+    (10, 2, 64, 64, dict(lam=1e-3, max_iter=30, theta=0.0)),                 # no over-relaxation
+    (11, 3, 48, 64, dict(lam=1e-3, max_iter=40, b0=(0.0, 0.0, 1.0))),        # B0 normal to the slices: D = 1/3 off k = 0
 ]
 
 
