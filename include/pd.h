@@ -118,6 +118,12 @@ typedef struct {
                           round's later steps, so results do not depend on the
                           round length.                                          */
   int flags;           /* PD_FLAG_* */
+  const char* tune_cache; /* path of a text file of autotuner choices, one line
+                          "nx ny variant rows cols" per slice shape: read at
+                          pd_create if it exists (lines that pd_tune_set would
+                          reject are skipped), rewritten after every pd_tune
+                          and pd_tune_set.  NULL: the PD_TUNE_CACHE environment
+                          variable if set, else no file.  The string is copied. */
 } pd_config;
 
 /* One reconstruction: a volume of nz slices of ny x nx voxels (Eq. (1)). */

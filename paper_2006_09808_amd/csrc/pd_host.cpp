@@ -507,6 +507,7 @@ struct pd_ctx {
     int rows = 0, cols = 0;
   };
   std::map<std::pair<int, int>, Tuned> tuned;
+  std::string tune_cache;      // file of the choices ("" = none)
 
   // captured step graphs of the two-launch path, keyed by launch plan
   struct GraphEntry {
@@ -1406,6 +1407,53 @@ void worker_main(pd_ctx* c) {
   }
 }
 
+// The checks pd_tune_set applies to one choice.
+pd_status tune_choice_check(const pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
+  if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
+  if (variant >= 0 && !(nx == ny && variant < resident_variant_count(nx))) return PD_ERR_ARG;
+  if (rows > 0 && !rows_valid(rows, nx, ny, c->precision)) return PD_ERR_ARG;
+  if (cols > 0 && !cols_valid(cols, nx, ny, c->precision)) return PD_ERR_ARG;
+  return PD_OK;
+}
+
+// Autotuner choices on disk: one "nx ny variant rows cols" line per shape.
+// Reading skips lines that do not parse or that pd_tune_set would reject;
+// writing goes through a temporary file renamed over the old one, so a
+// reader never sees half a file.  Caller holds c->mu (save) or is pd_create.
+void load_tune_cache(pd_ctx* c) {
+  FILE* f = c->tune_cache.empty() ? nullptr : std::fopen(c->tune_cache.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    int nx, ny, v, r, cl;
+    if (std::sscanf(line, "%d %d %d %d %d", &nx, &ny, &v, &r, &cl) != 5) continue;
+    if (tune_choice_check(c, nx, ny, v, r, cl) != PD_OK) continue;
+    pd_ctx::Tuned tn;
+    tn.res_variant = v >= 0 ? v : 0;
+    tn.rows = r > 0 ? r : 0;
+    tn.cols = cl > 0 ? cl : 0;
+    c->tuned[{nx, ny}] = tn;
+  }
+  std::fclose(f);
+}
+
+void save_tune_cache(const pd_ctx* c) {
+  if (c->tune_cache.empty()) return;
+  const std::string tmp = c->tune_cache + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  bool ok = true;
+  for (auto& kv : c->tuned) {
+    const int nx = kv.first.first, ny = kv.first.second;
+    // as pd_tune_get reports it: no resident variant for other shapes
+    const int v = (nx == ny && resident_variant_count(nx) > 0) ? kv.second.res_variant : -1;
+    ok &= std::fprintf(f, "%d %d %d %d %d\n", nx, ny, v, kv.second.rows, kv.second.cols) > 0;
+  }
+  ok &= std::fclose(f) == 0;
+  if (ok) std::rename(tmp.c_str(), c->tune_cache.c_str());
+  else std::remove(tmp.c_str());
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1474,6 +1522,10 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->precision = cfg->precision;
   c->nslots = cfg->max_slots > 0 ? cfg->max_slots : kDefaultSlots;
   c->time_kernels = (cfg->flags & PD_FLAG_TIME_KERNELS) != 0;
+  if (cfg->tune_cache) c->tune_cache = cfg->tune_cache;
+  else if (const char* env = std::getenv("PD_TUNE_CACHE")) c->tune_cache = env;
+  c->cfg.tune_cache = nullptr;   // the caller's string is not kept
+  load_tune_cache(c.get());
   c->arena.init((char*)cfg->arena, cfg->arena_bytes);
 
   c->range_cap = 4 * (size_t)c->nslots + 4096;
@@ -1873,6 +1925,7 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
     }
   }
   c->tuned[{nx, ny}] = tn;
+  save_tune_cache(c);
   int n = 0;
   for (auto& t : all) {
     if (entries && n < max_entries) entries[n] = t;
@@ -1884,10 +1937,8 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
 
 pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
   if (!c) return PD_ERR_ARG;
-  if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
-  if (variant >= 0 && !(nx == ny && variant < resident_variant_count(nx))) return PD_ERR_ARG;
-  if (rows > 0 && !rows_valid(rows, nx, ny, c->precision)) return PD_ERR_ARG;
-  if (cols > 0 && !cols_valid(cols, nx, ny, c->precision)) return PD_ERR_ARG;
+  pd_status st = tune_choice_check(c, nx, ny, variant, rows, cols);
+  if (st != PD_OK) return st;
   std::lock_guard<std::mutex> ex(c->exec_mu);   // between scheduling steps
   std::lock_guard<std::mutex> lk(c->mu);
   pd_ctx::Tuned tn;
@@ -1895,6 +1946,7 @@ pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols
   tn.rows = rows > 0 ? rows : 0;
   tn.cols = cols > 0 ? cols : 0;
   c->tuned[{nx, ny}] = tn;
+  save_tune_cache(c);
   return PD_OK;
 }
 

@@ -38,7 +38,7 @@ class PdConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("arena", ctypes.c_void_p), ("arena_bytes", ctypes.c_size_t),
                 ("max_slots", ctypes.c_int), ("precision", ctypes.c_int),
-                ("step_iters", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("step_iters", ctypes.c_int), ("flags", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class PdRequest(ctypes.Structure):
@@ -182,7 +182,7 @@ class Solver:
 
     def __init__(self, arena_bytes=1 << 30, device=0, max_slots=0, precision="fp32",
                  step_iters=0, time_kernels=False, resident=True, fenced_exchange=False, graphs=True,
-                 stream=None, arena=None):
+                 stream=None, arena=None, tune_cache=None):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -202,6 +202,7 @@ class Solver:
         cfg.step_iters = int(step_iters)
         cfg.flags = ((PD_FLAG_TIME_KERNELS if time_kernels else 0) | (0 if resident else PD_FLAG_NO_RESIDENT)
                      | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0) | (0 if graphs else PD_FLAG_NO_GRAPHS))
+        cfg.tune_cache = os.fsencode(tune_cache) if tune_cache else None
         self._ctx = ctypes.c_void_p()
         st = self.lib.pd_create(ctypes.byref(cfg), ctypes.byref(self._ctx))
         if st != PD_OK:

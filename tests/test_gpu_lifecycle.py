@@ -96,3 +96,23 @@ def test_destroy_with_requests_in_flight(torch_mod):
     ref, _ = oracle.solve(d2.astype(np.float64), **w2.solver_params())
     assert info["status"] == pd.PD_OK
     assert np.linalg.norm(chi.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-4
+
+
+def test_tune_cache_file_round_trip(torch_mod, tmp_path):
+    """pd_config.tune_cache: pd_tune and pd_tune_set write the choices, a new
+    context reads them back; lines that do not parse or that pd_tune_set would
+    reject are skipped."""
+    import paper_2006_09808_amd as pd
+    path = tmp_path / "tune.txt"
+    with pd.Solver(arena_bytes=1 << 30, device=0, tune_cache=str(path)) as s:
+        s.tune(128, 128, 8, iters=10)
+        choice = s.tune_get(128, 128)
+        s.tune_set(96, 64, -1, 8, 8)
+    text = path.read_text()
+    _say("tune cache:\n" + text)
+    assert text.count("\n") == 2 and "128 128 " in text and "96 64 " in text
+    path.write_text(text + "not a choice\n128 128 99 0 0\n96 64 -1 7 0\n")
+    with pd.Solver(arena_bytes=256 << 20, device=0, tune_cache=str(path)) as s2:
+        assert s2.tune_get(128, 128) == choice
+        got = s2.tune_get(96, 64)
+        assert (got["rows"], got["cols"]) == (8, 8)
