@@ -57,6 +57,8 @@ def parse():
                     help="length of the Poisson serving run (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-arena-gb", type=float, default=64.0)
+    ap.add_argument("--serve-stress-seconds", type=float, default=15.0,
+                    help="length of a second serving run under a 2 GB arena (0, or --serve-seconds 0: skip it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only time a plain device copy of BYTES bytes (the reference kernel for "
                          "scaling hardware byte counters) and exit")
@@ -560,6 +562,10 @@ def main():
         out["workloads"]["dipole3d_256x256x64_500it"] = volume3d_workload()
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
+    if a.serve_seconds > 0 and a.serve_stress_seconds > 0:
+        # admission under pressure: the same request mix with a 2 GB arena,
+        # where requests wait for arena space
+        out["serving_2GB_arena"] = serving(a.serve_rate, a.serve_stress_seconds, 2.0)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_sample_slices, a.cpu_sample_iters)
     print(json.dumps(out), flush=True)
