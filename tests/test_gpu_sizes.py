@@ -201,3 +201,19 @@ def test_tv_solve_bluestein_odd_stack(solver, torch_mod):
     err = rel_l2(chi, ref)
     _say("tv 43x27x5 relL2 %.3e" % err)
     assert err <= REL_TOL
+
+
+def test_largest_slices_768_direct_and_383_bluestein(solver, torch_mod):
+    """Maximum sizes: 768 x 768 slices (the longest direct plan on both axes)
+    and 383 x 383 slices (the longest length without a direct plan, run as
+    Bluestein convolutions on 768-point transforms along both axes)."""
+    for nx, ny, iters in ((768, 768, 4), (383, 383, 4)):
+        _say("largest: %dx%dx1, %d iterations" % (nx, ny, iters))
+        w, delta = make_case(230 + nx, 1, ny, nx, max_iter=iters)
+        sp = w.solver_params()
+        chi, info = gpu_solve(solver, torch_mod, delta, **sp)
+        assert info["status"] == 0 and info["iterations"] == iters
+        ref, _ = oracle.solve(delta.astype(np.float64), **sp)
+        err = rel_l2(chi, ref)
+        _say("  relL2 %.3e" % err)
+        assert err <= REL_TOL
