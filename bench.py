@@ -107,10 +107,12 @@ def flops_per_voxel_iteration(n):
     return 10.0 * math.log2(n) + 13.0
 
 
-def measured_traffic(kernel):
-    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` from the
-    committed rocprofv3 summaries, or None if the kernel sources changed since
-    the counters were taken."""
+def measured_traffic(kernel, variant=None):
+    """Scaled FETCH_SIZE + WRITE_SIZE bytes per launch of `kernel` (for the
+    resident kernel: of resident variant `variant`) from the committed
+    rocprofv3 summaries, with the summary's file name, or (None, None) if no
+    summary was taken with the current kernel sources.  Not measured in the
+    run that reports it."""
     import glob
     import hashlib
     h = hashlib.sha256()
@@ -119,7 +121,7 @@ def measured_traffic(kernel):
             with open(os.path.join(ROOT, "paper_2006_09808_amd", "csrc", f), "rb") as fh:
                 h.update(fh.read())
     except OSError:
-        return None
+        return None, None
     for prof in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(prof) as fh:
             for l in fh:
@@ -127,9 +129,12 @@ def measured_traffic(kernel):
                 if not l.startswith("traffic:"):
                     continue
                 rec = json.loads(l[len("traffic:"):])
-                if rec.get("kernel") == kernel and rec.get("sources_sha256_16") == h.hexdigest()[:16]:
-                    return rec["read_bytes"] + rec["write_bytes"]
-    return None
+                if rec.get("kernel") != kernel or rec.get("sources_sha256_16") != h.hexdigest()[:16]:
+                    continue
+                if variant is not None and rec.get("variant") != variant:
+                    continue
+                return rec["read_bytes"] + rec["write_bytes"], os.path.relpath(prof, ROOT)
+    return None, None
 
 
 def serving(rate, seconds, arena_gb):
@@ -335,7 +340,7 @@ def tv_workload(nz=64, n=256, iters=500, reps=3):
         if nl:
             bpp = TV_COL_BYTES_PER_POINT if name == "tv_column" else TV_ROW_BYTES_PER_POINT
             out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
-                                    "bytes_per_launch": bpp * pts / nl, "traffic": measured_traffic(name)}
+                                    "bytes_per_launch": bpp * pts / nl, "traffic": measured_traffic(name)[0]}
     return out
 
 
@@ -397,7 +402,10 @@ def cpu_baseline(w, nslices, iters):
     vit = nslices * NX * NY * iters
     out = {"value": vit / dt, "unit": "voxel-iterations/s", "cores": int(threads), "kind": "oracle",
            "sample": "%d of %d slices (256x256), %d of %d iterations, FP64 dense-DFT oracle, %.1f s"
-                     % (nslices, NZ, iters, ITERS, dt)}
+                     % (nslices, NZ, iters, ITERS, dt),
+           "host_cpus": os.cpu_count(), "blas_threads": int(threads),
+           "threads_note": "the dense DFTs are BLAS matrix products on blas_threads threads; the "
+                           "point-wise steps run on one"}
     # the same sample solved on the GPU (FP32, the autotuned launch
     # configuration of the bench shape), against the oracle's iterate
     import torch
@@ -517,21 +525,38 @@ def main():
         # streaming model's bytes, so the kernel is rated on arithmetic
         n, ms, pts = kt["resident"]
         tflops = flops_per_voxel_iteration(NX) * 2 * pts / (ms * 1e-3) / 1e12
-        roofline = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": FP32_NONPACKED_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tflops / FP32_NONPACKED_TFLOPS,
-                    "peak_derivation": "256 CUs x 4 SIMD x 16 lanes x FMA x 2.4 GHz (no packed FP32 emitted)",
-                    "peak_published_packed": FP32_PEAK_TFLOPS,
-                    "frac_of_published_packed": tflops / FP32_PEAK_TFLOPS,
-                    "traffic": measured_traffic(dom),
+        variant = tune_choice["variant"]
+        vrow = [t for t in tune_table if t["path"] == "resident" and t["variant"] == variant]
+        traffic, traffic_src = measured_traffic(dom, variant)
+        roofline = {"bound": "alu", "kernel": dom, "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS,
+                    "peak_note": "published FP32 vector peak (packed FP32, two FMAs per lane)",
+                    "peak_nonpacked": FP32_NONPACKED_TFLOPS, "frac_nonpacked": tflops / FP32_NONPACKED_TFLOPS,
+                    "peak_nonpacked_derivation": "256 CUs x 4 SIMD x 16 lanes x FMA x 2.4 GHz: the issue "
+                                                 "ceiling of the non-packed FP32 this build emits",
+                    "variant": variant,
+                    "variant_shape": ({"workgroups_per_pair": vrow[0]["team"], "threads": vrow[0]["threads"]}
+                                      if vrow else None),
+                    "traffic": traffic,
+                    "traffic_source": (None if traffic is None else
+                                       "%s: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE of this kernel and variant "
+                                       "with the current sources, scaled by a 1 GiB copy; not measured in "
+                                       "this run" % traffic_src),
                     "flops_per_voxel_iteration": flops_per_voxel_iteration(NX),
                     "avg_ms": kernels[dom]["avg_ms"],
-                    "hbm_model": {"bytes_per_voxel_iteration": 24, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                                  "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                                  "bytes_per_launch": kernels[dom]["bytes_per_launch"]},
+                    "streaming_model": {
+                        "bytes_per_voxel_iteration": 24,
+                        "bytes_per_launch": kernels[dom]["bytes_per_launch"],
+                        "equivalent_GBs": achieved,
+                        "note": "bytes a kernel streaming its state through HBM every iteration would move "
+                                "per second at this speed; this kernel keeps its state on chip, so it is "
+                                "not a bandwidth measurement"},
                     "kernels": kernels}
     else:
+        traffic, traffic_src = measured_traffic(dom)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "traffic_source": None if traffic is None else "%s (not measured in this run)" % traffic_src,
                     "avg_ms": kernels[dom]["avg_ms"], "bytes_per_launch": kernels[dom]["bytes_per_launch"],
                     "kernels": kernels}
     out = {

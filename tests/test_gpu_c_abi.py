@@ -9,6 +9,7 @@ import subprocess
 import numpy as np
 import pytest
 
+import _parity
 import oracle
 import pd_inputs
 
@@ -43,9 +44,7 @@ def test_c_program_matches_oracle_and_binding(tmp_path):
     chi_c = np.fromfile(fout, dtype=np.float32).reshape(nz, ny, nx)
     sp = dict(lam=lam, tau=1.4, sigma=1.4, theta=1.0, max_iter=iters)
     ref, _ = oracle.solve(delta.astype(np.float64), **sp)
-    err = float(np.linalg.norm(chi_c - ref) / np.linalg.norm(ref))
-    _say("  relL2 vs oracle %.3e" % err)
-    assert err <= 1e-4
+    _parity.check(chi_c, ref, "C program chi")
     with pd.Solver(arena_bytes=256 << 20, device=0) as s:
         chi_py, _ = s.solve(torch.from_numpy(delta).to("cuda:0"), **sp)
     np.testing.assert_array_equal(chi_py.cpu().numpy(), chi_c)

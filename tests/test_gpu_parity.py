@@ -2,18 +2,19 @@
 
 Inputs are seeded phantoms; the field map is made by the oracle's own forward
 operator and rounded to FP32, and the same FP32 field map goes to both sides.
-Bar: relative L2 error on chi <= 1e-4 after a fixed iteration count
-(FP32 GPU arithmetic against FP64; the expected error is ~1e-6).
+Bar (tests/_parity.py): relative L2 error on chi <= 1e-4 after a fixed
+iteration count, and every voxel within 1e-4 of max|chi_oracle| (FP32 GPU
+arithmetic against FP64; the observed errors are ~1e-6 of either).
 """
 import numpy as np
 import pytest
 
+import _parity
 import oracle
 import pd_inputs
 
 pytestmark = pytest.mark.gpu
 
-REL_TOL = 1e-4
 
 
 def _say(*a):
@@ -79,9 +80,7 @@ def gpu_solve(solver, torch, delta, **params):
     return chi.cpu().numpy().astype(np.float64), info
 
 
-def rel_l2(a, b):
-    nb = np.linalg.norm(b)
-    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+rel_l2 = _parity.rel_l2
 
 
 APPLY_CASES = [
@@ -105,9 +104,7 @@ def test_forward_operator_matches_oracle(solver, torch_mod, nz, ny, nx, b0, vox)
     ref = oracle.forward(x.astype(np.float64), b0=b0, voxel=vox)
     xt = torch_mod.from_numpy(x).to("cuda:0")
     out = solver.apply_kernel(xt, b0=b0, voxel=vox).cpu().numpy().astype(np.float64)
-    err = rel_l2(out, ref)
-    _say("  relL2 %.3e" % err)
-    assert err <= 1e-5
+    _parity.check(out, ref, "A x", rel_tol=1e-5, vox_tol=1e-5)
 
 
 SOLVE_CASES = [
@@ -139,11 +136,9 @@ def test_fixed_iterations_match_oracle(request, torch_mod, path, seed, nz, ny, n
     sp = w.solver_params()
     got, info = gpu_solve(solver, torch_mod, delta, **sp)
     ref, iref = oracle.solve(delta.astype(np.float64), **sp)
-    err = rel_l2(got, ref)
-    _say("  relL2 %.3e  max-abs %.3e ppm  P %.8e (oracle %.8e)" % (err, np.abs(got - ref).max(),
-                                                                  info["primal"], iref["primal"]))
+    _say("  P %.8e (oracle %.8e)" % (info["primal"], iref["primal"]))
     assert info["iterations"] == iref["iterations"] == sp["max_iter"]
-    assert err <= REL_TOL
+    _parity.check(got, ref, "chi")
     assert info["primal"] == pytest.approx(iref["primal"], rel=1e-4)
 
 
@@ -158,11 +153,10 @@ def test_first_iterations_match_oracle(request, torch_mod, path, iters, nz, ny, 
     sp = w.solver_params()
     got, info = gpu_solve(solver, torch_mod, delta, **sp)
     ref, iref = oracle.solve(delta.astype(np.float64), **sp)
-    err = rel_l2(got, ref)
-    _say("[%s] %dx%dx%d after %d: relL2 %.3e gap %.6e (oracle %.6e)" % (path, nx, ny, nz, iters, err,
-                                                                      info["rel_gap"], iref["rel_gap"]))
+    _say("[%s] %dx%dx%d after %d: gap %.6e (oracle %.6e)" % (path, nx, ny, nz, iters,
+                                                           info["rel_gap"], iref["rel_gap"]))
     assert info["iterations"] == iref["iterations"] == iters
-    assert err <= REL_TOL
+    _parity.check(got, ref, "chi")
     assert info["rel_gap"] == pytest.approx(iref["rel_gap"], rel=1e-4)
     assert info["primal"] == pytest.approx(iref["primal"], rel=1e-5)
 
@@ -175,9 +169,7 @@ def test_config1_plain_64x64(solver, torch_mod):
     _say("config1 64x64x1, %d iterations" % sp["max_iter"])
     got, info = gpu_solve(solver, torch_mod, delta, **sp)
     ref, iref = oracle.solve(delta.astype(np.float64), **sp)
-    err = rel_l2(got, ref)
-    _say("  relL2 %.3e  max-abs %.3e ppm" % (err, np.abs(got - ref).max()))
-    assert err <= REL_TOL
+    _parity.check(got, ref, "chi")
     assert info["iterations"] == 200
 
 
@@ -198,7 +190,7 @@ def test_gap_report_matches_oracle(request, torch_mod, path, shape):
     assert info["primal"] == pytest.approx(iref["primal"], rel=1e-5)
     assert info["dual"] == pytest.approx(iref["dual"], rel=1e-4)
     assert abs(info["rel_gap"] - iref["rel_gap"]) <= 1e-4 * max(1.0, abs(iref["rel_gap"]))
-    assert rel_l2(got, ref) <= REL_TOL
+    _parity.check(got, ref, "chi")
 
 
 @pytest.mark.parametrize("shape", [(3, 32, 64), (3, 64, 64), (2, 128, 128)])
@@ -222,7 +214,7 @@ def test_identity_kernel_tolerance_stop(solver, torch_mod, shape):
     ref_same, _ = oracle.solve(delta.astype(np.float64), kind="identity",
                                **dict((k, v) for k, v in sp.items() if k not in ("kernel", "gap_tol")
                                       and k != "max_iter"), max_iter=info["iterations"])
-    assert rel_l2(got, ref_same) <= REL_TOL
+    _parity.check(got, ref_same, "chi")
     closed = np.sign(delta) * np.maximum(np.abs(delta.astype(np.float64)) - 0.2, 0.0)
     assert np.max(np.abs(got - closed)) <= 1e-3
 
@@ -333,7 +325,7 @@ def test_budget_and_queueing(torch_mod):
             info = s.poll(t, -1)
             assert info["status"] == pd.PD_OK and info["iterations"] == 25
             ref, _ = oracle.solve(d.astype(np.float64), **w.solver_params())
-            assert rel_l2(chi.cpu().numpy().astype(np.float64), ref) <= REL_TOL
+            _parity.check(chi.cpu().numpy().astype(np.float64), ref, "chi")
 
 
 def test_batched_config_full_size_sampled(solver, torch_mod):
@@ -349,9 +341,7 @@ def test_batched_config_full_size_sampled(solver, torch_mod):
     assert info["iterations"] == 500
     for z in (0, 37, 63):
         ref, _ = oracle.solve(delta[z:z + 1].astype(np.float64), **sp)
-        err = rel_l2(got[z:z + 1], ref)
-        _say("  slice %d relL2 %.3e max-abs %.3e" % (z, err, np.abs(got[z] - ref[0]).max()))
-        assert err <= REL_TOL
+        _parity.check(got[z:z + 1], ref, "slice %d" % z)
     # the launch configuration the benchmark times: the autotuner's choice for
     # this shape (every resident variant does the same arithmetic, so equal bits)
     import paper_2006_09808_amd as pd
@@ -377,9 +367,7 @@ def test_resident_batch_split_across_launches(solver, torch_mod):
     assert info["iterations"] == 30
     for z in (0, 63, 64, 65):
         ref, _ = oracle.solve(delta[z:z + 1].astype(np.float64), **sp)
-        err = rel_l2(got[z:z + 1], ref)
-        _say("  slice %d relL2 %.3e" % (z, err))
-        assert err <= REL_TOL
+        _parity.check(got[z:z + 1], ref, "slice %d" % z)
 
 
 @pytest.mark.parametrize("n", [64, 128, 192, 256])
@@ -459,7 +447,7 @@ def test_autotune_configurations_agree(torch_mod, n, nz):
             got, info = gpu_solve(s, torch_mod, delta, **sp)
             np.testing.assert_array_equal(got, ref)
         oref, _ = oracle.solve(delta.astype(np.float64), **sp)
-        assert rel_l2(ref, oref) <= REL_TOL
+        _parity.check(ref, oref, "chi")
         with pytest.raises(pd.PdError):
             s.tune_set(nx, ny, 99, 0, 0)
         with pytest.raises(pd.PdError):

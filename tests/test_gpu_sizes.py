@@ -8,21 +8,19 @@ against the same FP64 oracle as every other shape.
 import numpy as np
 import pytest
 
+import _parity
 import oracle
 import pd_inputs
 from test_gpu_parity import make_case, gpu_solve
 
 pytestmark = pytest.mark.gpu
 
-REL_TOL = 1e-4
-
 
 def _say(*a):
     print(*a, flush=True)
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+rel_l2 = _parity.rel_l2
 
 
 @pytest.fixture(scope="module")
@@ -80,9 +78,7 @@ def test_forward_operator_any_size(solver, torch_mod, shape):
     x = rng.normal(size=(nz, ny, nx)).astype(np.float32)
     ref = oracle.forward(x.astype(np.float64), b0=b0, voxel=vox)
     out = solver.apply_kernel(torch_mod.from_numpy(x).to("cuda:0"), b0=b0, voxel=vox).cpu().numpy()
-    err = rel_l2(out.astype(np.float64), ref)
-    _say("  relL2 %.3e" % err)
-    assert err <= 1e-5
+    _parity.check(out, ref, "A x", rel_tol=1e-5, vox_tol=1e-5)
 
 
 @pytest.mark.parametrize("shape", [OPERATOR_SHAPES[0], OPERATOR_SHAPES[3], OPERATOR_SHAPES[6], OPERATOR_SHAPES[8],
@@ -94,9 +90,7 @@ def test_forward_operator_any_size_fp64(solver64, torch_mod, shape):
     x = rng.normal(size=(nz, ny, nx))
     ref = oracle.forward(x, b0=b0, voxel=vox)
     out = solver64.apply_kernel(torch_mod.from_numpy(x).to("cuda:0"), b0=b0, voxel=vox).cpu().numpy()
-    err = rel_l2(out, ref)
-    _say("fp64 operator %s relL2 %.3e" % (ids(shape), err))
-    assert err <= 1e-12
+    _parity.check(out, ref, "fp64 A x %s" % ids(shape), rel_tol=1e-12, vox_tol=1e-12)
 
 
 SOLVE_SHAPES = [
@@ -117,10 +111,8 @@ def test_l1_solve_any_size_matches_oracle(solver, torch_mod, case):
     chi, info = gpu_solve(solver, torch_mod, delta, **sp)
     assert info["status"] == 0 and info["iterations"] == iters
     ref, rinfo = oracle.solve(delta.astype(np.float64), **sp)
-    err = rel_l2(chi, ref)
-    _say("  relL2 %.3e  max-abs %.3e ppm; gap %.6e vs %.6e" % (err, float(np.max(np.abs(chi - ref))),
-                                                           info["rel_gap"], rinfo["rel_gap"]))
-    assert err <= REL_TOL
+    _say("  gap %.6e vs %.6e" % (info["rel_gap"], rinfo["rel_gap"]))
+    _parity.check(chi, ref, "chi")
     assert info["rel_gap"] == pytest.approx(rinfo["rel_gap"], rel=1e-3)
 
 
@@ -131,9 +123,7 @@ def test_tv_solve_any_size_matches_oracle(solver, torch_mod):
     chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
     assert info["status"] == 0
     ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
-    err = rel_l2(chi, ref)
-    _say("tv 132x128x3 relL2 %.3e" % err)
-    assert err <= REL_TOL
+    _parity.check(chi, ref, "tv 132x128x3 chi")
 
 
 def test_gap_stop_on_bluestein_shape(solver, torch_mod):
@@ -156,7 +146,7 @@ def test_gap_stop_on_bluestein_shape(solver, torch_mod):
     assert abs(info["iterations"] - rinfo["iterations"]) <= 5
     osp["max_iter"], osp["gap_tol"] = info["iterations"], 0.0
     ref_same, _ = oracle.solve(delta.astype(np.float64), **osp)
-    assert rel_l2(chi, ref_same) <= REL_TOL
+    _parity.check(chi, ref_same, "chi")
 
 
 def test_mixed_sizes_in_one_batch_equal_their_solo_runs(solver, torch_mod):
@@ -184,9 +174,7 @@ def test_l1_solve_bluestein_fp64(solver64, torch_mod):
     d = torch_mod.from_numpy(delta.astype(np.float64)).to("cuda:0")
     chi, info = solver64.solve(d, **sp)
     ref, rinfo = oracle.solve(delta.astype(np.float64), **sp)
-    err = rel_l2(chi.cpu().numpy(), ref)
-    _say("fp64 bluestein solve relL2 %.3e" % err)
-    assert err <= 1e-10
+    _parity.check(chi.cpu().numpy(), ref, "fp64 bluestein chi", rel_tol=1e-10, vox_tol=1e-10)
     assert info["rel_gap"] == pytest.approx(rinfo["rel_gap"], rel=1e-9)
 
 
@@ -198,9 +186,7 @@ def test_tv_solve_bluestein_odd_stack(solver, torch_mod):
     chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
     assert info["status"] == 0
     ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
-    err = rel_l2(chi, ref)
-    _say("tv 43x27x5 relL2 %.3e" % err)
-    assert err <= REL_TOL
+    _parity.check(chi, ref, "tv 43x27x5 chi")
 
 
 def test_largest_slices_768_direct_and_383_bluestein(solver, torch_mod):
@@ -214,6 +200,4 @@ def test_largest_slices_768_direct_and_383_bluestein(solver, torch_mod):
         chi, info = gpu_solve(solver, torch_mod, delta, **sp)
         assert info["status"] == 0 and info["iterations"] == iters
         ref, _ = oracle.solve(delta.astype(np.float64), **sp)
-        err = rel_l2(chi, ref)
-        _say("  relL2 %.3e" % err)
-        assert err <= REL_TOL
+        _parity.check(chi, ref, "%dx%d chi" % (nx, ny))

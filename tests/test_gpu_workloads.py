@@ -5,11 +5,11 @@ oracle for the GPU's iteration count must match the GPU's slice."""
 import numpy as np
 import pytest
 
+import _parity
 import oracle
 import pd_inputs
 
 pytestmark = pytest.mark.gpu
-REL_TOL = 1e-4
 
 
 def _say(*a):
@@ -24,8 +24,7 @@ def torch_mod():
     return torch
 
 
-def rel_l2(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+rel_l2 = _parity.rel_l2
 
 
 def test_uneven_batch_with_gap_tolerance(torch_mod):
@@ -54,9 +53,7 @@ def test_uneven_batch_with_gap_tolerance(torch_mod):
         z = w.shape[0] // 2
         fixed = dict(sp, gap_tol=0.0, max_iter=info["iterations"])
         ref, _ = oracle.solve(d[z:z + 1].cpu().numpy().astype(np.float64), **fixed)
-        err = rel_l2(chi[z:z + 1].cpu().numpy().astype(np.float64), ref)
-        _say("    slice %d relL2 %.3e" % (z, err))
-        assert err <= REL_TOL
+        _parity.check(chi[z:z + 1].cpu().numpy(), ref, "slice %d" % z)
 
 
 def test_precision_fp32_fp64_gpu_and_oracle(torch_mod):
@@ -77,14 +74,8 @@ def test_precision_fp32_fp64_gpu_and_oracle(torch_mod):
     c32 = c32.cpu().numpy().astype(np.float64)
     c64 = c64.cpu().numpy()
     assert i32["iterations"] == i64["iterations"] == 800
-    e_32_64 = rel_l2(c32, c64)
-    _say("FP32 GPU vs FP64 GPU over 128 slices: relL2 %.3e max-abs %.3e ppm" % (e_32_64, np.abs(c32 - c64).max()))
-    assert e_32_64 <= REL_TOL
+    _parity.check(c32, c64, "FP32 GPU vs FP64 GPU, 128 slices")
     for z in (0, 64, 127):
         ref, _ = oracle.solve(d32[z:z + 1].astype(np.float64), **sp)
-        e32 = rel_l2(c32[z:z + 1], ref)
-        e64 = rel_l2(c64[z:z + 1], ref)
-        _say("  slice %d: FP32 GPU relL2 %.3e (max-abs %.3e ppm); FP64 GPU relL2 %.3e (max-abs %.3e ppm)"
-             % (z, e32, np.abs(c32[z] - ref[0]).max(), e64, np.abs(c64[z] - ref[0]).max()))
-        assert e32 <= REL_TOL
-        assert e64 <= 1e-10
+        _parity.check(c32[z:z + 1], ref, "slice %d FP32 GPU vs oracle" % z)
+        _parity.check(c64[z:z + 1], ref, "slice %d FP64 GPU vs oracle" % z, rel_tol=1e-10, vox_tol=1e-10)

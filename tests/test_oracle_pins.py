@@ -541,3 +541,100 @@ def test_planted_ignored_slice_thickness_is_caught(monkeypatch):
            lambda nx, ny, nz, b0=(0, 1, 0), voxel=(1, 1), voxel_z=1.0: good(nx, ny, nz, b0, voxel, 1.0))
     with pytest.raises(AssertionError):
         test_dipole3d_kernel_hand_derived("dipole3d_3x1x2_b0z_dz2.txt")
+
+
+def dense_pd_with_dual(A, d, lam, tau, sigma, theta, iters):
+    """dense_pd, also returning the dual iterate y_n."""
+    x = np.zeros_like(d)
+    y = np.zeros_like(d)
+    xb = x.copy()
+    for _ in range(iters):
+        y = (y + sigma * (A @ xb - d)) / (1 + sigma)
+        v = x - tau * (A @ y)
+        xn = np.sign(v) * np.maximum(np.abs(v) - tau * lam, 0)
+        xb = xn + theta * (xn - x)
+        x = xn
+    return x, y
+
+
+def gap_from_definition(A, d, lam, x, y):
+    """Primal objective, rescaled dual objective and relative gap written out
+    from their definitions on a dense operator: P = 1/2||A x - d||^2 +
+    lam||x||_1; s = min(1, lam / ||A y||_inf) makes s y dual-feasible for
+    max -1/2||y||^2 - <y, d> s.t. ||A y||_inf <= lam."""
+    r = A @ x - d
+    P = 0.5 * r @ r + lam * np.sum(np.abs(x))
+    m = np.max(np.abs(A @ y))
+    s = 1.0 if m == 0 else min(1.0, lam / m)
+    Dual = -0.5 * s * s * (y @ y) - s * (y @ d)
+    return P, Dual, (P - Dual) / max(P, 1e-300)
+
+
+@pytest.mark.parametrize("iters", [1, 7, 40])
+def test_3d_objective_and_gap_equal_their_dense_definitions(iters):
+    """The 3-D kernel's primal, dual and gap, pinned to a dense A3 from cosine
+    sums and the gap's definition (no DFT, no oracle code): a gap evaluated
+    with the slice-wise operator, a dropped term or a wrong scale fails."""
+    b0, vox, dz = (0.3, 0.5, 0.8), (1.0, 0.8), 1.6
+    D = O.dipole_kernel3(4, 3, 2, b0, vox, dz)
+    A = dense_A3_from_cosines(D)
+    rng = np.random.default_rng(12 + iters)
+    d = rng.normal(size=(2, 3, 4)) * 2
+    lam, tau, sigma, theta = 0.05, 1.4, 1.4, 1.0
+    x, y = dense_pd_with_dual(A, d.ravel(), lam, tau, sigma, theta, iters)
+    P, Dual, rel = gap_from_definition(A, d.ravel(), lam, x, y)
+    _, info = O.solve(d, lam, tau, sigma, theta, iters, b0=b0, voxel=vox, kind="dipole3d", voxel_z=dz)
+    assert info["primal"] == pytest.approx(P, rel=1e-12)
+    assert info["dual"] == pytest.approx(Dual, rel=1e-11, abs=1e-13)
+    assert info["rel_gap"] == pytest.approx(rel, rel=1e-10, abs=1e-13)
+    # the same numbers from the gap-checked run (checks every iteration)
+    _, info2 = O.solve(d, lam, tau, sigma, theta, iters, gap_tol=1e-300, check_every=1, b0=b0, voxel=vox,
+                       kind="dipole3d", voxel_z=dz)
+    assert info2["iterations"] == iters
+    assert info2["primal"] == pytest.approx(P, rel=1e-12)
+    assert info2["rel_gap"] == pytest.approx(rel, rel=1e-10, abs=1e-13)
+
+
+def test_3d_pd_reaches_exact_lasso_minimum_4x3x2():
+    """Converged 3-D solve against an independent lasso solver (L-BFGS-B on
+    the dense A3) whose optimality is certified by the KKT conditions: the
+    oracle's objective reaches the certified minimum and its gap closes."""
+    b0, vox, dz = (0.3, 0.5, 0.8), (1.0, 0.8), 1.6
+    D = O.dipole_kernel3(4, 3, 2, b0, vox, dz)
+    A = dense_A3_from_cosines(D)
+    rng = np.random.default_rng(13)
+    d = rng.normal(size=(2, 3, 4))
+    lam = 0.1
+    x_star, _ = lasso_exact(A, d.ravel(), lam)
+    p_star = lasso_objective(A, d.ravel(), lam, x_star)
+    g = A.T @ (d.ravel() - A @ x_star)
+    on = np.abs(x_star) > 1e-9
+    assert on.any()
+    assert np.max(np.abs(g[on] - lam * np.sign(x_star[on]))) < 1e-6
+    assert np.max(np.abs(g[~on])) <= lam - 1e-3          # strictly feasible off the support
+    chi, info = O.solve(d, lam=lam, max_iter=5000, b0=b0, voxel=vox, kind="dipole3d", voxel_z=dz)
+    assert lasso_objective(A, d.ravel(), lam, chi.ravel()) == pytest.approx(p_star, rel=1e-9)
+    assert info["primal"] == pytest.approx(p_star, rel=1e-9)
+    assert 0.0 <= info["rel_gap"] < 1e-8
+    np.testing.assert_allclose(A @ chi.ravel(), A @ x_star, atol=1e-5)
+
+
+def test_planted_slicewise_operator_in_3d_gap_is_caught(monkeypatch):
+    good = O.pd_oracle.duality_gap
+    # the gap evaluated with the slice-wise operator instead of the 3-D one
+    _plant(monkeypatch, "duality_gap", lambda chi, y, Ay, delta, D, lam, A=None: good(chi, y, Ay, delta, D, lam))
+    with pytest.raises(AssertionError):
+        test_3d_objective_and_gap_equal_their_dense_definitions(7)
+
+
+def test_planted_unscaled_dual_in_gap_is_caught(monkeypatch):
+    good = O.pd_oracle.duality_gap
+
+    def no_rescale(chi, y, Ay, delta, D, lam, A=None):
+        # the dual objective without the feasibility rescaling s
+        P, _, _ = good(chi, y, Ay, delta, D, lam, A)
+        Dual = -0.5 * float(np.sum(y * y)) - float(np.sum(y * delta))
+        return P, Dual, (P - Dual) / max(P, 1e-300)
+    _plant(monkeypatch, "duality_gap", no_rescale)
+    with pytest.raises(AssertionError):
+        test_3d_objective_and_gap_equal_their_dense_definitions(40)
