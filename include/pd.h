@@ -91,9 +91,25 @@ enum {
                                 workgroups of a team with agent-scope
                                 release/acquire (L2 write-back), even when
                                 they share an XCD                              */
-  PD_FLAG_NO_GRAPHS = 8      /* never replay a step of the two-launch path from
+  PD_FLAG_NO_GRAPHS = 8,     /* never replay a step of the two-launch path from
                                 a captured HIP graph                           */
+  PD_FLAG_TEST_BARRIER_GIVEUP = 16 /* test hook: resident-kernel team barriers
+                                poll only twice before they give up, which
+                                forces the recovery path below             */
 };
+/* Recovery from a resident launch that cannot complete.  The resident kernel
+ * synchronises the workgroups of a team with bounded spin barriers; if its
+ * workgroups are not all co-resident (other work holding CUs), a barrier
+ * gives up, every workgroup of the launch exits and later resident launches
+ * of the same scheduling round do nothing.  The context stays usable: the
+ * requests those launches covered restart from chi_0 = 0 on the two-launch
+ * path (no co-residency needed), which gives the same iterates up to
+ * rounding, and their slice shapes stay on that path for the rest of the
+ * context (pd_tune_set with a resident variant re-enables it).  The
+ * solver's state, kept on the GPU between steps as in the paper's
+ * device-resident scheme (Sec. II-D), is rebuilt from the field map, which
+ * stays valid until the ticket completes.  pd_recovery_stats counts these
+ * events. */
 
 typedef struct pd_ctx pd_ctx;     /* opaque, library-owned */
 
@@ -266,6 +282,10 @@ pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* c
 /* Scheduling steps of the two-launch path captured into HIP graphs, and
  * steps replayed from one, since pd_create. */
 pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays);
+
+/* Scheduling rounds in which a resident launch gave up, and requests
+ * restarted on the two-launch path because of it, since pd_create. */
+pd_status pd_recovery_stats(pd_ctx* c, int64_t* aborted_rounds, int64_t* restarted_requests);
 
 /* Bytes of arena currently in use (control blocks, resident requests' state,
  * and kernel tables: D grid and twiddles per kernel shape, which stay cached

@@ -26,6 +26,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <cstdio>
@@ -437,6 +438,7 @@ struct Job {
   int done_iters = 0;
   int run_iters = 0;        // iterations enqueued for it in the current round
   bool finished = false;
+  bool in_resident = false; // some resident launch of the current round covers it
   double knorm = 0.0;       // max |D| of the request's kernel grid
   pd_result res{};
 };
@@ -464,6 +466,8 @@ struct pd_ctx {
 
   std::mutex mu;               // queues, tickets, arena, tables
   std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_idle;   // signalled when the last in-flight API call leaves
+  int calls = 0;               // API calls inside the context (CallGuard), under mu
   std::mutex exec_mu;          // GPU submission (worker steps vs. pd_apply_kernel)
   Arena arena;
   std::map<TableKey, Table> tables;
@@ -508,6 +512,12 @@ struct pd_ctx {
   };
   std::map<std::pair<int, int>, Tuned> tuned;
   std::string tune_cache;      // file of the choices ("" = none)
+  // shapes whose resident launch gave up at a team barrier: the two-launch
+  // path only from then on (until pd_tune_set picks a resident variant
+  // again).  Read and written under exec_mu.
+  std::set<std::pair<int, int>> no_resident;
+  unsigned spin_limit = kSpinLimit;   // resident barriers' polls before giving up
+  int64_t aborted_rounds = 0, restarted_requests = 0;   // under exec_mu
 
   // captured step graphs of the two-launch path, keyed by launch plan
   struct GraphEntry {
@@ -536,6 +546,27 @@ bool hip_ok(pd_ctx* c, hipError_t e) {
   c->poisoned = PD_ERR_HIP;
   return false;
 }
+
+// Every entry point that uses a context counts itself in for its whole
+// duration, so pd_destroy, which may run on another thread, frees the
+// context only after the calls already inside have left.  A call that
+// arrives once pd_destroy has begun is refused (ok == false).
+struct CallGuard {
+  pd_ctx* c;
+  bool ok;
+  explicit CallGuard(pd_ctx* cc) : c(cc) {
+    std::lock_guard<std::mutex> lk(c->mu);
+    ok = !c->stopping;
+    if (ok) ++c->calls;
+  }
+  ~CallGuard() {
+    if (!ok) return;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (--c->calls == 0) c->cv_idle.notify_all();
+  }
+  CallGuard(const CallGuard&) = delete;
+  CallGuard& operator=(const CallGuard&) = delete;
+};
 
 // Tables whose last user has retired stay in the arena (uploaded), so the
 // next request of that kernel shape starts without rebuilding them; they are
@@ -939,7 +970,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     const bool z3 = g.first.nz3 > 0;
     const ResidentVariant* rv =
         (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv &&
-         !z3)
+         !z3 && !c->no_resident.count({nx, ny}))
             ? resident_variant(nx, tn.res_variant) : nullptr;
     int maxt = rv ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
     if (rv) {
@@ -970,6 +1001,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       L.rv = rv;
       L.range_off = (int)k;
       for (Job* j : g.second) {
+        j->in_resident = true;
         int p = 0;
         while (p < j->L.P) {
           if (L.npairs == maxt) {
@@ -1093,7 +1125,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     const int fenced = (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0;
     e = timed(2, pts, [&] {
       return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
-                          c->stream);
+                          c->spin_limit, c->stream);
     });
     if (step_err("resident launch", e) != hipSuccess) return e;
   }
@@ -1248,8 +1280,12 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
 // One scheduling round: steps enqueued back to back (run-ahead, while no
 // request waits for admission), then one read-back of every volume's control
 // block and one wait.  Returns with run_iters = iterations enqueued per job.
-hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued) {
-  for (auto& j : act) j->run_iters = 0;
+hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queued, bool* aborted) {
+  *aborted = false;
+  for (auto& j : act) {
+    j->run_iters = 0;
+    j->in_resident = false;
+  }
   StepEvents tev;
   hipError_t e = hipSuccess;
   int total = 0;
@@ -1278,8 +1314,40 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     }
   }
   if (step_err("round", e) != hipSuccess) return e;
-  if (*c->h_abort) return step_err("team barrier", hipErrorLaunchTimeOut);   // a team barrier gave up
+  *aborted = *c->h_abort != 0;   // a team barrier gave up
   return hipSuccess;
+}
+
+// Recovery from a resident launch whose team barrier gave up (its
+// workgroups were not all co-resident, e.g. while other work held CUs).
+// Every resident launch of the round from that one on did nothing, and the
+// state of the requests they cover is no longer one consistent iterate, so
+// each of those requests restarts from chi_0 = 0 (set-up again from its
+// field map, which stays valid until its ticket completes) and its shape
+// runs on the two-launch path, which needs no co-residency, from now on.
+// The other requests of the round are unaffected.  Caller holds exec_mu.
+hipError_t recover_round(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act,
+                         std::vector<std::shared_ptr<Job>>& restarted) {
+  std::vector<Job*> js;
+  for (auto& j : act) {
+    if (!j->in_resident) continue;
+    c->no_resident.insert({j->req.nx, j->req.ny});
+    j->done_iters = 0;
+    j->run_iters = 0;
+    restarted.push_back(j);
+    js.push_back(j.get());
+  }
+  c->aborted_rounds++;
+  c->restarted_requests += (int64_t)js.size();
+  if (std::getenv("PD_DEBUG"))
+    std::fprintf(stderr, "pd: a resident team barrier gave up; %zu request(s) restart on the two-launch path\n",
+                 js.size());
+  *c->h_abort = 0;
+  hipError_t e = launch_zero(c->d_abort, sizeof(int), c->stream);
+  for (Job* j : js)
+    if (e == hipSuccess) e = setup_job(c, *j);
+  if (e == hipSuccess && !js.empty()) e = launch_setup(c, js);
+  return e;
 }
 
 void finish_job(pd_ctx* c, Job& j, pd_status st) {
@@ -1359,12 +1427,15 @@ void worker_main(pd_ctx* c) {
     lk.unlock();
 
     hipError_t e;
-    std::vector<std::shared_ptr<Job>> retired;
+    std::vector<std::shared_ptr<Job>> retired, restarted;
     {
       std::lock_guard<std::mutex> ex(c->exec_mu);
-      e = run_step(c, act, queued);
+      bool aborted = false;
+      e = run_step(c, act, queued, &aborted);
+      if (e == hipSuccess && aborted) e = recover_round(c, act, restarted);
       if (e == hipSuccess) {
         for (auto& j : act) {
+          if (std::find(restarted.begin(), restarted.end(), j) != restarted.end()) continue;
           const Ctl& C = c->h_ctl[j->slot];
           // the final check always stops a volume; the cap test only guards
           // against a step that could not run it
@@ -1522,6 +1593,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->precision = cfg->precision;
   c->nslots = cfg->max_slots > 0 ? cfg->max_slots : kDefaultSlots;
   c->time_kernels = (cfg->flags & PD_FLAG_TIME_KERNELS) != 0;
+  if (cfg->flags & PD_FLAG_TEST_BARRIER_GIVEUP) c->spin_limit = 2;
   if (cfg->tune_cache) c->tune_cache = cfg->tune_cache;
   else if (const char* env = std::getenv("PD_TUNE_CACHE")) c->tune_cache = env;
   c->cfg.tune_cache = nullptr;   // the caller's string is not kept
@@ -1584,6 +1656,8 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
 
 pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* tickets) {
   if (!c || (n > 0 && (!r || !tickets)) || n < 0) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::vector<std::shared_ptr<Job>> js;
   size_t avail = c->arena.size() - align_up(c->ctl_bytes);
   for (int i = 0; i < n; ++i) {
@@ -1617,16 +1691,19 @@ pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* ticket
 
 pd_status pd_poll(pd_ctx* c, uint64_t ticket, pd_result* out, int timeout_ms) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);   // outlives the lock below: released after it
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::unique_lock<std::mutex> lk(c->mu);
   auto it = c->jobs.find(ticket);
   if (it == c->jobs.end()) return PD_ERR_TICKET;
   std::shared_ptr<Job> j = it->second;
-  auto done = [&] { return j->finished; };
+  // pd_destroy wakes every waiter: the ticket ends cancelled
+  auto done = [&] { return j->finished || c->stopping; };
   if (timeout_ms < 0)
     c->cv_done.wait(lk, done);
   else if (timeout_ms > 0)
     c->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done);
-  if (!j->finished) return PD_PENDING;
+  if (!j->finished) return c->stopping ? PD_ERR_CANCELLED : PD_PENDING;
   if (out) *out = j->res;
   c->jobs.erase(ticket);
   return j->res.status;
@@ -1638,6 +1715,7 @@ pd_status pd_destroy(pd_ctx* c) {
     std::lock_guard<std::mutex> lk(c->mu);
     c->stopping = true;
     c->cv_work.notify_all();
+    c->cv_done.notify_all();   // pd_poll waiters return PD_ERR_CANCELLED
   }
   if (c->worker.joinable()) c->worker.join();
   (void)hipSetDevice(c->device);
@@ -1647,6 +1725,12 @@ pd_status pd_destroy(pd_ctx* c) {
     for (auto& j : c->queue) finish_job(c, *j, PD_ERR_CANCELLED);
     for (auto& j : c->active) finish_job(c, *j, PD_ERR_CANCELLED);
     c->cv_done.notify_all();
+  }
+  {
+    // calls already inside the context (a waiting pd_poll, a pd_tune) leave
+    // before anything they touch is freed
+    std::unique_lock<std::mutex> lk(c->mu);
+    c->cv_idle.wait(lk, [&] { return c->calls == 0; });
   }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (auto& g : c->graphs)
@@ -1659,6 +1743,8 @@ pd_status pd_destroy(pd_ctx* c) {
 
 pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
   if (!c || !r) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
   pd_status ks = kernel_args(r);
   if (ks != PD_OK) return ks;
@@ -1746,6 +1832,8 @@ pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
 
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters) {
   if (!c || kind < 0 || kind >= pd_ctx::kKinds) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::lock_guard<std::mutex> lk(c->tmu);
   if (launches) *launches = c->t_launches[kind];
   if (total_ms) *total_ms = c->t_ms[kind];
@@ -1755,8 +1843,10 @@ pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_m
 
 pd_status pd_kernel_time_reset(pd_ctx* c) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::lock_guard<std::mutex> lk(c->tmu);
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < pd_ctx::kKinds; ++k) {
     c->t_launches[k] = 0;
     c->t_ms[k] = 0.0;
     c->t_points[k] = 0.0;
@@ -1767,6 +1857,8 @@ pd_status pd_kernel_time_reset(pd_ctx* c) {
 pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
                   int* n_entries) {
   if (!c || iters < 1 || nz < 1 || max_entries < 0) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
   if (n_entries) *n_entries = 0;
   pd_request r{};
@@ -1860,11 +1952,17 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
                                       c->stream);
           if (r2 != hipSuccess) return r2;
           return rv->launch(nteams, c->d_vols, dr, 1, c->d_ctl, c->d_counters, c->d_abort,
-                            (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0, c->stream);
+                            (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0, c->spin_limit, c->stream);
         }, &best);
-        if (e == hipSuccess && hipMemcpy(c->h_abort, c->d_abort, sizeof(int), hipMemcpyDeviceToHost) == hipSuccess &&
-            *c->h_abort)
-          e = hipErrorLaunchTimeOut;
+        if (e == hipSuccess) e = hipMemcpy(c->h_abort, c->d_abort, sizeof(int), hipMemcpyDeviceToHost);
+        if (e == hipSuccess && *c->h_abort) {
+          // a team barrier gave up: this variant is not a candidate (the
+          // context stays usable)
+          *c->h_abort = 0;
+          e = launch_zero(c->d_abort, sizeof(int), c->stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+          continue;
+        }
         // time per iteration of all P pairs (nteams pairs per launch)
         pd_tune_entry t{nx, ny, nz, iters, 0, v, rv->team(), rv->threads(), 0, 0, best * (double)P / nteams};
         all.push_back(t);
@@ -1937,10 +2035,13 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
 
 pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   pd_status st = tune_choice_check(c, nx, ny, variant, rows, cols);
   if (st != PD_OK) return st;
   std::lock_guard<std::mutex> ex(c->exec_mu);   // between scheduling steps
   std::lock_guard<std::mutex> lk(c->mu);
+  if (variant >= 0) c->no_resident.erase({nx, ny});   // an explicit resident choice re-enables it
   pd_ctx::Tuned tn;
   tn.res_variant = variant >= 0 ? variant : 0;
   tn.rows = rows > 0 ? rows : 0;
@@ -1952,6 +2053,8 @@ pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols
 
 pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::lock_guard<std::mutex> lk(c->mu);
   pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
   if (variant) *variant = (nx == ny && resident_variant_count(nx) > 0) ? tn.res_variant : -1;
@@ -1962,14 +2065,28 @@ pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* c
 
 pd_status pd_graph_stats(pd_ctx* c, int64_t* captures, int64_t* replays) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::lock_guard<std::mutex> ex(c->exec_mu);
   if (captures) *captures = c->graph_captures;
   if (replays) *replays = c->graph_replays;
   return PD_OK;
 }
 
+pd_status pd_recovery_stats(pd_ctx* c, int64_t* aborted_rounds, int64_t* restarted_requests) {
+  if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
+  std::lock_guard<std::mutex> ex(c->exec_mu);
+  if (aborted_rounds) *aborted_rounds = c->aborted_rounds;
+  if (restarted_requests) *restarted_requests = c->restarted_requests;
+  return PD_OK;
+}
+
 pd_status pd_arena_usage(pd_ctx* c, size_t* used, int* resident, int* queued) {
   if (!c) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
   std::lock_guard<std::mutex> lk(c->mu);
   if (used) *used = c->arena.used();
   if (resident) *resident = (int)c->active.size();

@@ -183,8 +183,13 @@ constexpr int kMaxTeamSlots = 2048;
 inline size_t counter_bytes(size_t team_slots) {
   return (team_slots + kXcds + 1) * kCounterStride * sizeof(unsigned);
 }
+// Polls a resident-launch barrier makes before it gives up and raises the
+// launch's abort flag (each poll sleeps about 128 cycles, so the default is
+// of the order of a second; a test can pass a handful to force the give-up).
+constexpr unsigned kSpinLimit = 1u << 22;
 typedef hipError_t (*resident_launch_fn)(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
-                                         unsigned* counters, int* abort_flag, int fenced, hipStream_t st);
+                                         unsigned* counters, int* abort_flag, int fenced, unsigned spin_limit,
+                                         hipStream_t st);
 struct ResidentVariant {
   int n;
   resident_launch_fn launch;

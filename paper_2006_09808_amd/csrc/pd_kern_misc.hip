@@ -27,7 +27,7 @@ PD_DECL(768)
 
 #define PD_DECL_RES(N, V)                                                                                   \
   hipError_t launch_resident_##N##_##V(int, const Vol*, const Range*, int, Ctl*, unsigned*, int*, int,    \
-                                       hipStream_t);                                                     \
+                                       unsigned, hipStream_t);                                           \
   int resident_max_teams_##N##_##V();                                                                    \
   int resident_team_##N##_##V();                                                                         \
   int resident_threads_##N##_##V();

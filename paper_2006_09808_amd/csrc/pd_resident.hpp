@@ -28,8 +28,6 @@
 
 namespace pdk {
 
-constexpr unsigned kSpinLimit = 1u << 22;
-
 // Raw buffer access: a per-thread 32-bit byte offset plus a wave-uniform one
 // (an SGPR), so the strided exchange-buffer addresses cost no vector
 // registers across the iteration loop.  Out-of-range offsets read 0 and drop
@@ -67,12 +65,12 @@ struct ExAddr {
 // Arrive at a team barrier and wait for `target` arrivals in total; thread 0
 // only.  Returns false once the spin limit is hit or another workgroup aborted.
 __device__ __forceinline__ bool arrive_wait(unsigned* cnt, unsigned add, unsigned target, unsigned mask,
-                                            unsigned* seen, int* abort_flag) {
+                                            unsigned* seen, int* abort_flag, unsigned spin_limit) {
   unsigned v = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
   unsigned spins = 0;
   while ((v & mask) < target) {
     __builtin_amdgcn_s_sleep(2);
-    if (++spins > kSpinLimit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    if (++spins > spin_limit || __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
       __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -87,7 +85,7 @@ __device__ __forceinline__ bool arrive_wait(unsigned* cnt, unsigned add, unsigne
 // agent-scope protocol (members on different XCDs).  Returns false in all
 // threads once any workgroup has aborted.
 __device__ __forceinline__ bool team_barrier(unsigned* cnt, unsigned target, int* abort_flag, int* lds_flag,
-                                             bool fenced) {
+                                             bool fenced, unsigned spin_limit) {
   // this wave's stores have reached L2 (the compiler may not move memory
   // operations across the signal fences)
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -97,7 +95,7 @@ __device__ __forceinline__ bool team_barrier(unsigned* cnt, unsigned target, int
   if (threadIdx.x == 0) {
     if (fenced) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     unsigned seen;
-    int ok = arrive_wait(cnt, 1u, target, 0xffffffffu, &seen, abort_flag) ? 1 : 0;
+    int ok = arrive_wait(cnt, 1u, target, 0xffffffffu, &seen, abort_flag, spin_limit) ? 1 : 0;
     if (fenced) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *lds_flag = ok;
   }
@@ -132,7 +130,8 @@ struct Resident {
 template <int NX, int NY, int TEAM, int NT>
 __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
-                                                 int* __restrict__ abort_flag, int nteams, int force_fenced) {
+                                                 int* __restrict__ abort_flag, int nteams, int force_fenced,
+                                                 unsigned spin_limit) {
   using R = Resident<NX, NY, TEAM, NT>;
   using FR = typename R::FR;
   using FC = typename R::FC;
@@ -153,6 +152,9 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
   const int rounds = (int)gridDim.x / (kXcds * TEAM);
   unsigned* tickets = counters + (size_t)rounds * kXcds * kCounterStride;   // per-XCD tickets, grid counter
   __shared__ int s_team, s_member, s_fenced;
+  // a launch earlier in the same round gave up: this one does nothing (the
+  // host restarts every request of the round's resident launches)
+  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   if (tid == 0) {
     const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
     unsigned ticket = 0xffffffffu;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
                                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned seen = 0;
     int fen = 1;
-    if (!arrive_wait(tickets + kXcds * kCounterStride, 1u, gridDim.x, 0xffffffffu, &seen, abort_flag)) {
+    if (!arrive_wait(tickets + kXcds * kCounterStride, 1u, gridDim.x, 0xffffffffu, &seen, abort_flag, spin_limit)) {
       fen = -1;
     } else {
       bool balanced = true;
@@ -289,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
         }
       }
     }
-    ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced);
+    ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
     if (!ok) break;
     // ---------------- row phase ----------------
     {
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
       }
     }
     if (!last || check) {
-      ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced);
+      ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
       if (!ok) break;
     }
   }
@@ -411,8 +413,11 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
     }
   }
 
+  // a team barrier gave up: the state of this launch's requests is dropped
+  // (they restart on the two-launch path), so nothing is written back
+  if (!ok) return;
   // ---- write the state back (chi already written on a check) ----
-  if (!(ok && check)) {
+  if (!check) {
 #pragma unroll
     for (int q = 0; q < R::NQO; ++q)
 #pragma unroll
@@ -434,11 +439,11 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
 // hipErrorCooperativeLaunchTooLarge if they cannot all be co-resident.
 template <int NX, int NY, int TEAM, int NT>
 hipError_t launch_resident_t(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
-                             unsigned* counters, int* abort_flag, int fenced, hipStream_t st) {
+                             unsigned* counters, int* abort_flag, int fenced, unsigned spin_limit, hipStream_t st) {
   const int rounds = (nteams + kXcds - 1) / kXcds;
   const int grid = rounds * kXcds * TEAM;
-  void* args[] = {(void*)&vols,     (void*)&ranges,     (void*)&nranges, (void*)&ctl,
-                  (void*)&counters, (void*)&abort_flag, (void*)&nteams,  (void*)&fenced};
+  void* args[] = {(void*)&vols,     (void*)&ranges,     (void*)&nranges, (void*)&ctl,       (void*)&counters,
+                  (void*)&abort_flag, (void*)&nteams,   (void*)&fenced,  (void*)&spin_limit};
   return hipLaunchCooperativeKernel((const void*)k_resident<NX, NY, TEAM, NT>, dim3(grid), dim3(NT), args, 0, st);
 }
 
@@ -462,9 +467,9 @@ int resident_max_teams_t() {
   namespace pdk {                                                                                        \
   hipError_t launch_resident_##N##_##V(int nteams, const Vol* vols, const Range* ranges, int nranges,    \
                                        Ctl* ctl, unsigned* counters, int* abort_flag, int fenced,        \
-                                       hipStream_t st) {                                                 \
+                                       unsigned spin_limit, hipStream_t st) {                            \
     return launch_resident_t<N, N, TEAM, NT>(nteams, vols, ranges, nranges, ctl, counters, abort_flag,   \
-                                             fenced, st);                                                 \
+                                             fenced, spin_limit, st);                                     \
   }                                                                                                      \
   int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT>(); }                 \
   int resident_team_##N##_##V() { return TEAM; }                                                        \

@@ -21,6 +21,7 @@ PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY, PD_KERNEL_DIPOLE_3D = 0, 1, 2
 _KERNELS = {"dipole": PD_KERNEL_DIPOLE, "identity": PD_KERNEL_IDENTITY, "dipole3d": PD_KERNEL_DIPOLE_3D}
 PD_MODEL_L1, PD_MODEL_TV = 0, 1
 PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
+PD_FLAG_TEST_BARRIER_GIVEUP = 16
 KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z = 0, 1, 2, 3, 4, 5
 
 # lengths with a direct FFT plan; any other length 2..MAX_BLUESTEIN runs
@@ -31,7 +32,7 @@ MAX_BLUESTEIN = 384
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",
            "pd_validate", "pd_kernel_norm", "pd_apply_kernel", "pd_now",
            "pd_kernel_time", "pd_kernel_time_reset", "pd_graph_stats", "pd_arena_usage",
-           "pd_tune", "pd_tune_set", "pd_tune_get")
+           "pd_tune", "pd_tune_set", "pd_tune_get", "pd_recovery_stats")
 
 
 class PdConfig(ctypes.Structure):
@@ -97,6 +98,7 @@ def load_library(path=None):
     lib.pd_kernel_time_reset.argtypes = [c.c_void_p]
     lib.pd_arena_usage.argtypes = [c.c_void_p, c.POINTER(c.c_size_t), c.POINTER(c.c_int), c.POINTER(c.c_int)]
     lib.pd_graph_stats.argtypes = [c.c_void_p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+    lib.pd_recovery_stats.argtypes = [c.c_void_p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
     lib.pd_tune.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.POINTER(PdTuneEntry), c.c_int,
                             c.POINTER(c.c_int)]
     lib.pd_tune_set.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int]
@@ -104,7 +106,8 @@ def load_library(path=None):
                                 c.POINTER(c.c_int)]
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
                  "pd_kernel_norm", "pd_apply_kernel", "pd_kernel_time", "pd_kernel_time_reset",
-                 "pd_graph_stats", "pd_arena_usage", "pd_tune", "pd_tune_set", "pd_tune_get"):
+                 "pd_graph_stats", "pd_arena_usage", "pd_tune", "pd_tune_set", "pd_tune_get",
+                 "pd_recovery_stats"):
         getattr(lib, name).restype = c.c_int32
     if path is None:
         _lib = lib
@@ -182,7 +185,7 @@ class Solver:
 
     def __init__(self, arena_bytes=1 << 30, device=0, max_slots=0, precision="fp32",
                  step_iters=0, time_kernels=False, resident=True, fenced_exchange=False, graphs=True,
-                 stream=None, arena=None, tune_cache=None):
+                 stream=None, arena=None, tune_cache=None, barrier_giveup_test=False):
         import torch
         self._torch = torch
         self.lib = load_library()
@@ -201,7 +204,8 @@ class Solver:
         cfg.precision = self.precision
         cfg.step_iters = int(step_iters)
         cfg.flags = ((PD_FLAG_TIME_KERNELS if time_kernels else 0) | (0 if resident else PD_FLAG_NO_RESIDENT)
-                     | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0) | (0 if graphs else PD_FLAG_NO_GRAPHS))
+                     | (PD_FLAG_FENCED_EXCHANGE if fenced_exchange else 0) | (0 if graphs else PD_FLAG_NO_GRAPHS)
+                     | (PD_FLAG_TEST_BARRIER_GIVEUP if barrier_giveup_test else 0))
         cfg.tune_cache = os.fsencode(tune_cache) if tune_cache else None
         self._ctx = ctypes.c_void_p()
         st = self.lib.pd_create(ctypes.byref(cfg), ctypes.byref(self._ctx))
@@ -355,6 +359,16 @@ class Solver:
         if st != PD_OK:
             raise PdError(st, "pd_graph_stats")
         return int(cap.value), int(rep.value)
+
+    def recovery_stats(self):
+        """(scheduling rounds whose resident launch gave up at a team barrier,
+        requests restarted on the two-launch path because of it)."""
+        ab = ctypes.c_int64(0)
+        rs = ctypes.c_int64(0)
+        st = self.lib.pd_recovery_stats(self._ctx, ctypes.byref(ab), ctypes.byref(rs))
+        if st != PD_OK:
+            raise PdError(st, "pd_recovery_stats")
+        return int(ab.value), int(rs.value)
 
     def arena_usage(self):
         used = ctypes.c_size_t(0)

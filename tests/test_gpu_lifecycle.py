@@ -117,3 +117,47 @@ def test_tune_cache_file_round_trip(torch_mod, tmp_path):
         assert s2.tune_get(128, 128) == choice
         got = s2.tune_get(96, 64)
         assert (got["rows"], got["cols"]) == (8, 8)
+
+
+def test_resident_barrier_giveup_recovers(torch_mod):
+    """A resident launch whose team barrier gives up does not end the context:
+    its requests restart on the two-launch path and finish with the unforced
+    run's iterates up to rounding, a request of another shape in the same
+    rounds is unaffected (bitwise), and later requests of the shape keep to
+    the two-launch path.  The give-up is forced from the host: the context's
+    test flag lets every barrier poll only twice, so every workgroup still
+    exits through the kernel's own bounded wait."""
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    wa, da = _case(730, 6, 256, 256, 0)
+    wb, db = _case(731, 3, 96, 64, 0)
+    pa = dict(wa.solver_params(), max_iter=120, gap_tol=1e-12, check_every=40)
+    pb = dict(wb.solver_params(), max_iter=90)
+    ta, tb = torch.from_numpy(da).to("cuda:0"), torch.from_numpy(db).to("cuda:0")
+
+    def run(s):
+        oa, ob = torch.empty_like(ta), torch.empty_like(tb)
+        t = s.submit([(ta, oa, pa), (tb, ob, pb)])
+        ia, ib = s.poll(t[0], -1), s.poll(t[1], -1)
+        assert ia["status"] == pd.PD_OK and ib["status"] == pd.PD_OK
+        return oa.cpu().numpy(), ia, ob.cpu().numpy(), ib
+
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        ra, ira, rb, irb = run(s)
+        assert s.recovery_stats() == (0, 0)
+    with pd.Solver(arena_bytes=1 << 30, device=0, barrier_giveup_test=True) as s:
+        _say("PD_FLAG_TEST_BARRIER_GIVEUP: 256x256x6 (resident shape) beside 96x64x3")
+        ga, iga, gb, igb = run(s)
+        aborted, restarted = s.recovery_stats()
+        _say("aborted rounds %d, restarted requests %d" % (aborted, restarted))
+        assert aborted >= 1 and restarted >= 1
+        assert iga["iterations"] == ira["iterations"] == 120 and igb["iterations"] == irb["iterations"] == 90
+        _parity.check(ga, ra, "restarted request vs unforced run", rel_tol=1e-5, vox_tol=1e-5)
+        assert iga["primal"] == pytest.approx(ira["primal"], rel=1e-5)
+        np.testing.assert_array_equal(gb, rb)
+        ref, _ = oracle.solve(da.astype(np.float64), **dict(pa, gap_tol=0.0))
+        _parity.check(ga, ref, "restarted request vs oracle")
+        # the shape now runs on the two-launch path: no further give-up
+        ga2, iga2, _, _ = run(s)
+        assert s.recovery_stats() == (aborted, restarted)
+        np.testing.assert_array_equal(ga2, ga)
