@@ -65,7 +65,10 @@ def test_admission_waits_for_arena(torch_mod):
     torch = torch_mod
     cases = [make(200 + i, 8, 128, 128, lam=1e-3, max_iter=40) for i in range(6)]
     need = pd.validate(128, 128, 8)
-    with pd.Solver(arena_bytes=2 * need + (4 << 20), device=0) as s:
+    with pd.Solver(arena_bytes=1 << 30, device=0) as probe:
+        base, _, _ = probe.arena_usage()          # the context's own control block
+    # room for two requests and the shape's kernel table (about 66 KB), not three
+    with pd.Solver(arena_bytes=base + 2 * need + need // 2, device=0) as s:
         reqs = []
         for w, d in cases:
             dt = torch.from_numpy(d).to("cuda:0")
