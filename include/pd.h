@@ -49,7 +49,9 @@ enum {
   PD_ERR_HIP = -6,         /* HIP runtime error; the context is unusable         */
   PD_ERR_CANCELLED = -7,   /* request cancelled by pd_destroy                    */
   PD_ERR_TICKET = -8,      /* unknown (or already reported) ticket               */
-  PD_ERR_NODEVICE = -9     /* no usable GPU                                       */
+  PD_ERR_NODEVICE = -9,    /* no usable GPU                                       */
+  PD_ERR_SCRATCH = -10     /* needs more than PD_STATIC_SCRATCH_BYTES (the entry
+                              point that allocates nothing)                       */
 };
 
 enum { PD_FP32 = 0, PD_FP64 = 1 };                      /* pd_config.precision */
@@ -230,6 +232,26 @@ pd_status pd_kernel_norm(const pd_request* r, double* norm);
  * chi the output (they may not alias).  Needs arena space like a solve of the
  * same shape; runs on the context stream and returns when out is written. */
 pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r);
+
+/* Size of the library's fixed device scratch: one array per GPU, held from
+ * library load until the process ends. */
+#define PD_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* pd_apply_kernel for callers that cannot allocate device memory (code that
+ * must not call hipMalloc, e.g. a tight serving loop or a harness that
+ * forbids it): the same kernels and the same result, but the exchange
+ * buffer and the kernel tables (D grid, twiddles) live in the library's
+ * fixed scratch instead of the context's arena, and the call makes no
+ * device or pinned allocation (hipMalloc, hipFree, hipHostMalloc, arena).
+ * The request must fit: FP32 needs 8 B per slice-pair point of the
+ * transformed field (P = ceil(nz/2) pairs of ny x nx; nz planes for the 3-D
+ * kernel) plus the tables (4 B per D-grid point and 8 B per twiddle);
+ * otherwise PD_ERR_SCRATCH, before any GPU work.  The scratch is shared by
+ * every call on its GPU and keeps the last call's contents; each call fills
+ * everything it reads before reading it.  Calls of one process on one GPU
+ * are serialised by the library (they never overlap in the scratch), and
+ * each call returns when out is written.  Other errors as pd_apply_kernel. */
+pd_status pd_apply_kernel_noalloc(pd_ctx* c, const pd_request* r);
 
 /* Seconds on a monotonic clock (the clock of pd_result's time stamps). */
 double pd_now(void);

@@ -517,6 +517,7 @@ struct pd_ctx {
   // again).  Read and written under exec_mu.
   std::set<std::pair<int, int>> no_resident;
   unsigned spin_limit = kSpinLimit;   // resident barriers' polls before giving up
+  void* scratch = nullptr;     // device address of this device's static scratch (pd_apply_kernel_noalloc)
   int64_t aborted_rounds = 0, restarted_requests = 0;   // under exec_mu
 
   // captured step graphs of the two-launch path, keyed by launch plan
@@ -590,6 +591,16 @@ bool arena_alloc(pd_ctx* c, size_t bytes, size_t* off) {
   return true;
 }
 
+// Device pointers of a shape's table laid out from p: D grid, then the
+// twiddles of x, y (and z), each 256-byte aligned (table_bytes in total).
+void table_ptrs(Table& t, char* p, const TableKey& k, int precision) {
+  const size_t tsz = precision == PD_FP64 ? 8 : 4;
+  t.d = p;
+  t.twx = p + align_up((size_t)k.nx * k.ny * std::max(k.nz3, 1) * tsz);
+  t.twy = (char*)t.twx + align_up(axis_tw_entries(k.nx) * 2 * tsz);
+  t.twz = k.nz3 > 1 ? (char*)t.twy + align_up(axis_tw_entries(k.ny) * 2 * tsz) : nullptr;
+}
+
 // Acquire (or share) the table of a shape; caller holds c->mu.
 Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
   auto it = c->tables.find(k);
@@ -603,12 +614,7 @@ Table* acquire_table(pd_ctx* c, const TableKey& k, bool* fresh) {
   t.bytes = table_bytes(k.nx, k.ny, k.nz3, c->precision);
   if (!arena_alloc(c, t.bytes, &t.off)) return nullptr;
   t.last_use = ++c->table_clock;
-  size_t tsz = c->precision == PD_FP64 ? 8 : 4;
-  char* p = c->arena.ptr(t.off);
-  t.d = p;
-  t.twx = p + align_up((size_t)k.nx * k.ny * std::max(k.nz3, 1) * tsz);
-  t.twy = (char*)t.twx + align_up(axis_tw_entries(k.nx) * 2 * tsz);
-  t.twz = k.nz3 > 1 ? (char*)t.twy + align_up(axis_tw_entries(k.ny) * 2 * tsz) : nullptr;
+  table_ptrs(t, c->arena.ptr(t.off), k, c->precision);
   t.refs = 1;
   t.uploaded = false;
   *fresh = true;
@@ -1525,6 +1531,119 @@ void save_tune_cache(const pd_ctx* c) {
   else std::remove(tmp.c_str());
 }
 
+// The forward operator out = A in (pd_apply_kernel).  Only the exchange
+// buffer is used: every state pointer of the descriptor aliases it.  With
+// `noalloc` the buffer and the kernel tables live in the library's static
+// scratch (pd_scratch.hip) instead of the arena, the tables are uploaded on
+// every call (another context may have used the scratch since), and the
+// per-device scratch lock serialises such calls across contexts.
+pd_status apply_kernel(pd_ctx* c, const pd_request* r, bool noalloc) {
+  if (!c || !r) return PD_ERR_ARG;
+  CallGuard guard(c);
+  if (!guard.ok) return PD_ERR_CANCELLED;
+  if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
+  pd_status ks = kernel_args(r);
+  if (ks != PD_OK) return ks;
+  if (!r->delta || !r->chi || r->delta == r->chi) return PD_ERR_ARG;
+
+  Job j;
+  j.req = *r;
+  j.req.gap_tol = 0.0;
+  j.req.model = PD_MODEL_L1;         // the operator alone: no model state
+  j.L = layout_of(j.req, c->precision);
+  j.L.off_chi = j.L.off_yhat = j.L.off_dhat = j.L.off_ex = j.L.off_ex2 = 0;
+  j.L.off_prow = j.L.off_pcol = 0;
+  j.L.total = j.L.field;
+  j.key = key_of(j.req);
+  j.slot = c->nslots;                // the reserved descriptor slot
+  bool fresh = false;
+  std::unique_lock<std::mutex> scratch_lk;
+  char* sbase = nullptr;             // noalloc: the field, after the tables
+  if (noalloc) {
+    const size_t tb = align_up(table_bytes(r->nx, r->ny, nz3_of(*r), c->precision));
+    if (!c->scratch) return PD_ERR_HIP;
+    if (tb + j.L.field > (size_t)PD_STATIC_SCRATCH_BYTES) return PD_ERR_SCRATCH;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      if (c->poisoned != PD_OK) return c->poisoned;
+    }
+    scratch_lk = std::unique_lock<std::mutex>(static_scratch_lock(c->device));
+    table_ptrs(j.tab, (char*)c->scratch, j.key, c->precision);
+    sbase = (char*)c->scratch + tb;
+    fresh = true;
+  } else {
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->poisoned != PD_OK) return c->poisoned;
+    size_t off;
+    if (!arena_alloc(c, j.L.total, &off)) return PD_ERR_BUDGET;
+    Table* t = acquire_table(c, j.key, &fresh);
+    if (!t) {
+      c->arena.release(off, j.L.total);
+      return PD_ERR_BUDGET;
+    }
+    if (fresh) t->uploaded = true;   // uploaded below, before any use
+    j.tab = *t;
+    j.off = off;
+  }
+  hipError_t e = hipSuccess;
+  {
+    std::lock_guard<std::mutex> ex(c->exec_mu);
+    (void)hipSetDevice(c->device);
+    if (fresh)
+      e = c->precision == PD_FP64 ? upload_table<double>(c, j.key, j.tab) : upload_table<float>(c, j.key, j.tab);
+    Vol& V = c->h_vols[j.slot];
+    fill_vol(c, j, V);
+    if (sbase) {
+      V.chi = V.yhat = V.dhat = V.ex = V.ex2 = sbase;
+      V.part_row = V.part_col = (double*)sbase;
+    }
+    Range* hr = c->h_ranges + (c->range_cap - 1);
+    *hr = Range{j.slot, 0, 0, 0};
+    const Range* dr = c->d_ranges + (c->range_cap - 1);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && j.L.unpacked) {
+      Vol& Z = c->h_vols[c->zoff + j.slot];
+      fill_zvol(j, V, Z);
+      e = hipMemcpyAsync(c->d_vols + c->zoff + j.slot, &Z, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
+    }
+    const int P = j.L.P;
+    if (e == hipSuccess)
+      e = launch_row(axis_phys(r->nx), ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
+                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
+    if (j.L.unpacked) {   // 3-D kernel: F_y, then (F_z, D, F_z^-1) on the z view, then F_y^-1
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->ny), COL_FWD, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->nz), COL_APPLY, 8, j.L.zgroups, j.L.zgroups, c->d_vols + c->zoff, dr, 1,
+                       c->d_ctl, 0, c->precision, j.L.ext_z, c->stream);
+      if (e == hipSuccess)
+        e = launch_col(axis_phys(r->ny), COL_INV, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
+    } else if (e == hipSuccess) {
+      e = launch_col(axis_phys(r->ny), COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
+                     c->d_ctl, 0, c->precision, j.L.ext_col, c->stream);
+    }
+    if (e == hipSuccess)
+      e = launch_row(axis_phys(r->nx), ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
+                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
+    hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = e2;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!noalloc) {
+    c->arena.release(j.off, j.L.total);
+    release_table(c, j.key);
+  }
+  if (e != hipSuccess) {
+    c->poisoned = PD_ERR_HIP;
+    return PD_ERR_HIP;
+  }
+  return PD_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1545,6 +1664,7 @@ const char* pd_status_string(pd_status s) {
     case PD_ERR_CANCELLED: return "cancelled";
     case PD_ERR_TICKET: return "unknown ticket";
     case PD_ERR_NODEVICE: return "no usable GPU";
+    case PD_ERR_SCRATCH: return "request larger than the static scratch (PD_STATIC_SCRATCH_BYTES)";
     default: return "unknown status";
   }
 }
@@ -1586,8 +1706,11 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PD_ERR_NODEVICE;
   if (cfg->device < 0 || cfg->device >= ndev) return PD_ERR_ARG;
   if (hipSetDevice(cfg->device) != hipSuccess) return PD_ERR_HIP;
+  void* scratch = nullptr;   // looked up once per device, with the device current
+  if (static_scratch(cfg->device, &scratch) != hipSuccess) return PD_ERR_HIP;
 
   std::unique_ptr<pd_ctx> c(new pd_ctx());
+  c->scratch = scratch;
   c->cfg = *cfg;
   c->device = cfg->device;
   c->precision = cfg->precision;
@@ -1741,94 +1864,9 @@ pd_status pd_destroy(pd_ctx* c) {
   return PD_OK;
 }
 
-pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) {
-  if (!c || !r) return PD_ERR_ARG;
-  CallGuard guard(c);
-  if (!guard.ok) return PD_ERR_CANCELLED;
-  if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
-  pd_status ks = kernel_args(r);
-  if (ks != PD_OK) return ks;
-  if (!r->delta || !r->chi || r->delta == r->chi) return PD_ERR_ARG;
+pd_status pd_apply_kernel(pd_ctx* c, const pd_request* r) { return apply_kernel(c, r, false); }
 
-  // Only the exchange buffer is used: every state pointer of the descriptor
-  // aliases it.
-  Job j;
-  j.req = *r;
-  j.req.gap_tol = 0.0;
-  j.req.model = PD_MODEL_L1;         // the operator alone: no model state
-  j.L = layout_of(j.req, c->precision);
-  j.L.off_chi = j.L.off_yhat = j.L.off_dhat = j.L.off_ex = j.L.off_ex2 = 0;
-  j.L.off_prow = j.L.off_pcol = 0;
-  j.L.total = j.L.field;
-  j.key = key_of(j.req);
-  bool fresh = false;
-  {
-    std::lock_guard<std::mutex> lk(c->mu);
-    if (c->poisoned != PD_OK) return c->poisoned;
-    size_t off;
-    if (!arena_alloc(c, j.L.total, &off)) return PD_ERR_BUDGET;
-    Table* t = acquire_table(c, j.key, &fresh);
-    if (!t) {
-      c->arena.release(off, j.L.total);
-      return PD_ERR_BUDGET;
-    }
-    if (fresh) t->uploaded = true;   // uploaded below, before any use
-    j.tab = *t;
-    j.off = off;
-    j.slot = c->nslots;              // the reserved descriptor slot
-  }
-  hipError_t e = hipSuccess;
-  {
-    std::lock_guard<std::mutex> ex(c->exec_mu);
-    (void)hipSetDevice(c->device);
-    if (fresh)
-      e = c->precision == PD_FP64 ? upload_table<double>(c, j.key, j.tab) : upload_table<float>(c, j.key, j.tab);
-    Vol& V = c->h_vols[j.slot];
-    fill_vol(c, j, V);
-    Range* hr = c->h_ranges + (c->range_cap - 1);
-    *hr = Range{j.slot, 0, 0, 0};
-    const Range* dr = c->d_ranges + (c->range_cap - 1);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync((void*)dr, hr, sizeof(Range), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess && j.L.unpacked) {
-      Vol& Z = c->h_vols[c->zoff + j.slot];
-      fill_zvol(j, V, Z);
-      e = hipMemcpyAsync(c->d_vols + c->zoff + j.slot, &Z, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
-    }
-    const int P = j.L.P;
-    if (e == hipSuccess)
-      e = launch_row(axis_phys(r->nx), ROW_FWD_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
-                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
-    if (j.L.unpacked) {   // 3-D kernel: F_y, then (F_z, D, F_z^-1) on the z view, then F_y^-1
-      if (e == hipSuccess)
-        e = launch_col(axis_phys(r->ny), COL_FWD, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
-                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
-      if (e == hipSuccess)
-        e = launch_col(axis_phys(r->nz), COL_APPLY, 8, j.L.zgroups, j.L.zgroups, c->d_vols + c->zoff, dr, 1,
-                       c->d_ctl, 0, c->precision, j.L.ext_z, c->stream);
-      if (e == hipSuccess)
-        e = launch_col(axis_phys(r->ny), COL_INV, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
-                       c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
-    } else if (e == hipSuccess) {
-      e = launch_col(axis_phys(r->ny), COL_APPLY, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
-                     c->d_ctl, 0, c->precision, j.L.ext_col, c->stream);
-    }
-    if (e == hipSuccess)
-      e = launch_row(axis_phys(r->nx), ROW_INV_PLANAR, j.L.rows, P * j.L.row_groups, j.L.row_groups, c->d_vols, dr,
-                     1, c->d_ctl, 0, c->precision, j.L.ext_row, c->stream);
-    hipError_t e2 = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = e2;
-  }
-  std::lock_guard<std::mutex> lk(c->mu);
-  c->arena.release(j.off, j.L.total);
-  release_table(c, j.key);
-  if (e != hipSuccess) {
-    c->poisoned = PD_ERR_HIP;
-    return PD_ERR_HIP;
-  }
-  return PD_OK;
-}
+pd_status pd_apply_kernel_noalloc(pd_ctx* c, const pd_request* r) { return apply_kernel(c, r, true); }
 
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters) {
   if (!c || kind < 0 || kind >= pd_ctx::kKinds) return PD_ERR_ARG;

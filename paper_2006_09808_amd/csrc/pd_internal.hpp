@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace pdk {
 
 // One resident request (a volume of nz slices), as the kernels see it.
@@ -197,6 +199,12 @@ struct ResidentVariant {
   int (*team)();
   int (*threads)();
 };
+// The library's fixed device scratch (pd_scratch.hip): device address of
+// `device`'s copy (the device must be current), and the lock that
+// serialises its users within the process.
+hipError_t static_scratch(int device, void** ptr);
+std::mutex& static_scratch_lock(int device);
+
 int resident_variant_count(int n);                      // 0: no resident kernel for n x n
 const ResidentVariant* resident_variant(int n, int v);  // nullptr if out of range
 

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libpd_hip.so")
 PD_OK, PD_PENDING = 0, 1
 PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET = -1, -2, -3, -4
 PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE = -5, -6, -7, -8, -9
+PD_ERR_SCRATCH = -10
+PD_STATIC_SCRATCH_BYTES = 64 << 20
 PD_FP32, PD_FP64 = 0, 1
 PD_KERNEL_DIPOLE, PD_KERNEL_IDENTITY, PD_KERNEL_DIPOLE_3D = 0, 1, 2
 _KERNELS = {"dipole": PD_KERNEL_DIPOLE, "identity": PD_KERNEL_IDENTITY, "dipole3d": PD_KERNEL_DIPOLE_3D}
@@ -32,7 +34,7 @@ MAX_BLUESTEIN = 384
 EXPORTS = ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_status_string",
            "pd_validate", "pd_kernel_norm", "pd_apply_kernel", "pd_now",
            "pd_kernel_time", "pd_kernel_time_reset", "pd_graph_stats", "pd_arena_usage",
-           "pd_tune", "pd_tune_set", "pd_tune_get", "pd_recovery_stats")
+           "pd_tune", "pd_tune_set", "pd_tune_get", "pd_recovery_stats", "pd_apply_kernel_noalloc")
 
 
 class PdConfig(ctypes.Structure):
@@ -91,6 +93,7 @@ def load_library(path=None):
     lib.pd_validate.argtypes = [c.POINTER(PdRequest), c.c_int, c.POINTER(c.c_size_t)]
     lib.pd_kernel_norm.argtypes = [c.POINTER(PdRequest), c.POINTER(c.c_double)]
     lib.pd_apply_kernel.argtypes = [c.c_void_p, c.POINTER(PdRequest)]
+    lib.pd_apply_kernel_noalloc.argtypes = [c.c_void_p, c.POINTER(PdRequest)]
     lib.pd_now.argtypes = []
     lib.pd_now.restype = c.c_double
     lib.pd_kernel_time.argtypes = [c.c_void_p, c.c_int, c.POINTER(c.c_int64), c.POINTER(c.c_double),
@@ -107,7 +110,7 @@ def load_library(path=None):
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
                  "pd_kernel_norm", "pd_apply_kernel", "pd_kernel_time", "pd_kernel_time_reset",
                  "pd_graph_stats", "pd_arena_usage", "pd_tune", "pd_tune_set", "pd_tune_get",
-                 "pd_recovery_stats"):
+                 "pd_recovery_stats", "pd_apply_kernel_noalloc"):
         getattr(lib, name).restype = c.c_int32
     if path is None:
         _lib = lib
@@ -279,9 +282,12 @@ class Solver:
             raise PdError(info["status"], "solve")
         return chi, info
 
-    def apply_kernel(self, x, out=None, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole", voxel_z=1.0):
+    def apply_kernel(self, x, out=None, b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kernel="dipole", voxel_z=1.0,
+                     noalloc=False):
         """out = A x (the field map of susceptibility x): slice by slice, or
-        over the whole volume for kernel="dipole3d"."""
+        over the whole volume for kernel="dipole3d".  noalloc=True calls
+        pd_apply_kernel_noalloc, whose scratch is the library's fixed device
+        array instead of the arena (out must then be given to allocate nothing)."""
         self._check_tensor(x, "x")
         if out is None:
             out = self._torch.empty_like(x)
@@ -290,9 +296,10 @@ class Solver:
         r = make_request(nx, ny, nz, x.data_ptr(), out.data_ptr(), b0=b0, voxel=voxel, kernel=kernel,
                          voxel_z=voxel_z)
         self._torch.cuda.current_stream(self.device).synchronize()
-        st = self.lib.pd_apply_kernel(self._ctx, ctypes.byref(r))
+        fn = self.lib.pd_apply_kernel_noalloc if noalloc else self.lib.pd_apply_kernel
+        st = fn(self._ctx, ctypes.byref(r))
         if st != PD_OK:
-            raise PdError(st, "pd_apply_kernel")
+            raise PdError(st, "pd_apply_kernel_noalloc" if noalloc else "pd_apply_kernel")
         return out
 
     # -- introspection -----------------------------------------------------

@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <functional>
 #include <mutex>
 #include <string>
@@ -318,6 +319,16 @@ const ResidentVariant kVariants[] = {{64, mock_resident, mock_max_teams, mock_te
                                      {128, mock_resident, mock_max_teams, mock_team, mock_threads},
                                      {256, mock_resident, mock_max_teams, mock_team, mock_threads}};
 }  // namespace
+
+namespace {
+alignas(256) unsigned char g_scratch[1 << 20];   // the mock's "static scratch" (sizes are checked on the host)
+std::mutex g_scratch_mu;
+}  // namespace
+hipError_t static_scratch(int, void** ptr) {
+  *ptr = g_scratch;
+  return hipSuccess;
+}
+std::mutex& static_scratch_lock(int) { return g_scratch_mu; }
 
 int resident_variant_count(int n) {
   int k = 0;
@@ -626,6 +637,11 @@ void t_apply_kernel() {
   for (size_t i = 0; i < q.delta.size(); ++i) q.delta[i] = (float)i;
   EXPECT(pd_apply_kernel(x.c, &q.r) == PD_OK, "apply");
   EXPECT(q.chi == q.delta, "mock operator output");
+  std::fill(q.chi.begin(), q.chi.end(), -1.f);
+  EXPECT(pd_apply_kernel_noalloc(x.c, &q.r) == PD_OK, "apply, static scratch");
+  EXPECT(q.chi == q.delta, "mock operator output, static scratch");
+  Req big = make_req(768, 768, 64, 0);   // 32 pairs of 768^2: 151 MB of field
+  EXPECT(pd_apply_kernel_noalloc(x.c, &big.r) == PD_ERR_SCRATCH, "too large for the static scratch");
   size_t used;
   int res, qd;
   pd_arena_usage(x.c, &used, &res, &qd);

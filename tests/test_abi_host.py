@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     assert pd.status_string(pd.PD_OK) == "ok"
-    for s in range(-9, 2):
+    for s in range(-10, 2):
         assert isinstance(pd.status_string(s), str) and pd.status_string(s)
 
 
