@@ -189,12 +189,19 @@ typedef struct {
   double t_submit, t_start, t_done;   /* seconds on pd_now()'s clock              */
 } pd_result;
 
-/* Create a context on cfg->device.  The arena must be device memory of that
- * device of at least arena_bytes and stay allocated until pd_destroy returns.
+/* Create a context on cfg->device: the device-side home of every request's
+ * data and iteration state for the whole solve (Sec. II-D: intermediate data
+ * and the per-slice state variables stay in GPU memory, so no transfer sits
+ * inside the iteration).  The arena must be device memory of that device of
+ * at least arena_bytes and stay allocated until pd_destroy returns.
  * Errors: PD_ERR_ARG (null/invalid field), PD_ERR_NODEVICE, PD_ERR_HIP. */
 pd_status pd_create(const pd_config* cfg, pd_ctx** out);
 
-/* Submit n requests; never blocks on the GPU.  On PD_OK tickets[0..n-1] hold
+/* Hand n reconstructions to the GPU (Sec. II-B, step (2): the field map
+ * already lives in device memory, so "moving" it is admission into the
+ * arena) to be iterated together with every other resident request, the
+ * slices of all of them in parallel (Sec. II-C, strategies (2) and (3)).
+ * Submit n requests; never blocks on the GPU.  On PD_OK tickets[0..n-1] hold
  * one ticket per request, and each request is admitted as soon as a slot and
  * enough arena are free (FIFO), then iterated together with every other
  * resident request.  Validation is all-or-nothing: on an error no request of
@@ -202,14 +209,22 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out);
  * (PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET, PD_ERR_HIP). */
 pd_status pd_solve_batch(pd_ctx* c, const pd_request* r, int n, uint64_t* tickets);
 
-/* Wait up to timeout_ms (< 0: forever, 0: just look) for a ticket.  Returns
+/* The result hand-back of Sec. II-B, step (6): a request's end point is
+ * decided on the GPU per volume (Sec. II-D), its chi written once into the
+ * caller's device buffer, and this call reports it.
+ * Wait up to timeout_ms (< 0: forever, 0: just look) for a ticket.  Returns
  * PD_PENDING while it runs; once finished, fills *out (if non-null), returns
  * out->status and forgets the ticket (a second poll gives PD_ERR_TICKET). */
 pd_status pd_poll(pd_ctx* c, uint64_t ticket, pd_result* out, int timeout_ms);
 
-/* Cancel queued and running requests (their tickets end PD_ERR_CANCELLED and
- * their chi is left unwritten), wait for the GPU, free library resources.
- * The arena stays the caller's.  Accepts NULL. */
+/* End of the device residency that pd_create began (Sec. II-D).  Cancel
+ * queued and running requests (their tickets end PD_ERR_CANCELLED and their
+ * chi is left unwritten), wait for the GPU, free library resources.  Calls
+ * already inside the context on other threads (a pd_poll waiting on a
+ * ticket, a pd_tune) return first, pd_poll with PD_ERR_CANCELLED; calls that
+ * start after pd_destroy has begun return PD_ERR_CANCELLED, and no call may
+ * use the context once pd_destroy has returned.  The arena stays the
+ * caller's.  Accepts NULL. */
 pd_status pd_destroy(pd_ctx* c);
 
 /* Static, human-readable name of a status. */

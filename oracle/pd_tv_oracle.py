@@ -11,14 +11,16 @@ What it computes (Sec. II-A, Eq. (1) and the PD pseudocode), per 2-D slice:
 
     minimise over chi   lam/2 || W (D chi - delta) ||_2^2  +  || M G chi ||_1
 
-with K = [W D ; M G], the data term F1(z) = lam/2 ||z - W delta||^2, the
-regulariser F2(v) = sum over voxels of |v(r)|_2 (isotropic) and no own term
-for chi.  The iteration follows the pseudocode's order:
-
-    p      <- (p + sigma (W D chibar - W delta)) / (1 + sigma / lam)   prox of F1*
-    q      <- v / max(1, |v|),  v = q + sigma M G chibar (per voxel)   prox of F2*
-    chi'   <- chi - tau D* W* p - tau G* M* q                          primal step
-    chibar <- chi' + theta (chi' - chi)                                over-relaxation
+It is the Chambolle-Pock primal-dual method of Sec. II-A applied to the
+saddle-point form of that problem.  Stack the two linear maps into
+K chi = (W D chi, M G chi) and write the problem as F(K chi) with
+F(z, v) = F1(z) + F2(v), F1(z) = lam/2 ||z - W delta||^2 and F2(v) the sum
+over voxels of the Euclidean norm of the gradient 2-vector v(r); chi has no
+own term.  One iteration is then three maps, each written below from its
+definition: a proximal step on the dual variable y = (p, q) for F* (which
+splits into F1* acting on p and F2* acting on q), a plain gradient step on
+chi along -K* y (the prox of the zero function is the identity), and the
+over-relaxed point chibar at which the next dual step evaluates K.
 
 Readings of the paper used here (it is silent or ambiguous on these points):
   * lam weights the data term, as Eq. (1) prints it and as the pseudocode's
@@ -49,7 +51,7 @@ import numpy as np
 from .pd_oracle import apply_A, dipole_kernel, kernel_norm
 
 __all__ = ["grad", "grad_adj", "grad_norm_bound", "check_steps_tv", "objective_tv",
-           "prox_data_dual", "proj_unit_ball", "solve_tv"]
+           "prox_data_dual", "proj_unit_ball", "apply_K", "apply_K_adj", "prox_dual_tv", "solve_tv"]
 
 
 # ---------------------------------------------------------------------------
@@ -130,12 +132,36 @@ def proj_unit_ball(vx, vy):
 
 
 # ---------------------------------------------------------------------------
+# The stacked operator K = [W D ; M G] and its adjoint
+# ---------------------------------------------------------------------------
+
+def apply_K(x, W, M, D, voxel=(1.0, 1.0)):
+    """K x = (W D x, M g_x, M g_y): the data-term image and the masked
+    gradient field of x."""
+    gx, gy = grad(x, voxel)
+    return W * apply_A(x, D), M * gx, M * gy
+
+
+def apply_K_adj(p, qx, qy, W, M, D, voxel=(1.0, 1.0)):
+    """K* (p, q) = D* W* p + G* M* q, with D, W and M real and diagonal in
+    their own domains (D* = D since the kernel is real and even)."""
+    return apply_A(W * p, D) + grad_adj(M * qx, M * qy, voxel)
+
+
+def prox_dual_tv(p, qx, qy, b, sigma, lam):
+    """prox of sigma F* at (p, q): F* is separable, so the data block takes
+    prox_data_dual and every voxel's gradient 2-vector its unit-ball
+    projection."""
+    return (prox_data_dual(p, b, sigma, lam),) + proj_unit_ball(qx, qy)
+
+
+# ---------------------------------------------------------------------------
 # The primal-dual solve
 # ---------------------------------------------------------------------------
 
 def solve_tv(delta, weight, mask, lam, tau, sigma, theta=1.0, max_iter=200,
              b0=(0.0, 1.0, 0.0), voxel=(1.0, 1.0), kind="dipole", history=None):
-    """PD iteration of the paper's pseudocode for Eq. (1) on a stack
+    """The primal-dual iteration of Sec. II-A for Eq. (1) on a stack
     delta[nz, ny, nx] with weights W and mask M of the same shape.
 
     Returns (chi, info) with info = {iterations, objective}.  If `history` is a
@@ -164,10 +190,12 @@ def solve_tv(delta, weight, mask, lam, tau, sigma, theta=1.0, max_iter=200,
     qy = np.zeros_like(delta)
     chibar = chi.copy()
     for _ in range(max_iter):
-        p = prox_data_dual(p + sigma * W * apply_A(chibar, D), b, sigma, lam)
-        gx, gy = grad(chibar, voxel)
-        qx, qy = proj_unit_ball(qx + sigma * M * gx, qy + sigma * M * gy)
-        chi_new = chi - tau * apply_A(W * p, D) - tau * grad_adj(M * qx, M * qy, voxel)
+        # dual: y <- prox_{sigma F*}(y + sigma K chibar)
+        kp, kx, ky = apply_K(chibar, W, M, D, voxel)
+        p, qx, qy = prox_dual_tv(p + sigma * kp, qx + sigma * kx, qy + sigma * ky, b, sigma, lam)
+        # primal: chi <- chi - tau K* y (no own term for chi)
+        chi_new = chi - tau * apply_K_adj(p, qx, qy, W, M, D, voxel)
+        # over-relaxation
         chibar = chi_new + theta * (chi_new - chi)
         chi = chi_new
         if history is not None:
