@@ -1117,30 +1117,38 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     return r;
   };
 
-  // resident launches first (each runs all K iterations of its pairs)
+  // The step's launches: resident launches first (each runs all K iterations
+  // of its pairs), then the two-launch path (K iterations of column and row
+  // launches), then the checks.  Replayed from a captured graph when the same
+  // plan recurs.
+  bool any_two = false, any_res = false;
   for (auto& L : launches) {
-    if (!L.resident) continue;
-    // team counters of every team slot of the launch (rounds of 8 teams),
-    // then the per-XCD tickets and the grid arrival counter
-    const size_t slots_ = (size_t)((L.npairs + kXcds - 1) / kXcds) * kXcds;
-    if ((e = launch_zero(c->d_counters, align_up(counter_bytes(slots_)), c->stream)) !=
-        hipSuccess)
-      return e;
-    const Range* rr = c->d_ranges + L.range_off;
-    double pts = (double)L.npairs * L.nx * L.ny * K;
-    const int fenced = (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0;
-    e = timed(2, pts, [&] {
-      return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
-                          c->spin_limit, c->stream);
-    });
-    if (step_err("resident launch", e) != hipSuccess) return e;
+    any_two |= !L.resident;
+    any_res |= L.resident;
   }
-  // two-launch path (K iterations of column and row launches), then the
-  // checks: replayed from a captured graph when the same plan recurs
-  bool any_two = false;
-  for (auto& L : launches) any_two |= !L.resident;
+  const int fenced = (c->cfg.flags & PD_FLAG_FENCED_EXCHANGE) ? 1 : 0;
+  auto enqueue_resident = [&](bool with_events) -> hipError_t {
+    for (auto& L : launches) {
+      if (!L.resident) continue;
+      // team counters of every team slot of the launch (rounds of 8 teams),
+      // then the per-XCD tickets and the grid arrival counter
+      const size_t slots_ = (size_t)((L.npairs + kXcds - 1) / kXcds) * kXcds;
+      hipError_t r = launch_zero(c->d_counters, align_up(counter_bytes(slots_)), c->stream);
+      if (r != hipSuccess) return r;
+      const Range* rr = c->d_ranges + L.range_off;
+      double pts = (double)L.npairs * L.nx * L.ny * K;
+      auto res = [&] {
+        return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
+                            c->spin_limit, c->stream);
+      };
+      r = with_events ? timed(2, pts, res) : res();
+      if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
+  };
   auto enqueue_rest = [&](bool with_events) -> hipError_t {
-    hipError_t r = hipSuccess;
+    hipError_t r = enqueue_resident(with_events);
+    if (r != hipSuccess) return r;
     if (any_two) {
       for (int it = 0; it < K; ++it) {
         for (auto& L : launches) {
@@ -1232,12 +1240,17 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     }
     return r;
   };
-  bool use_graph = any_two && !c->time_kernels && !(c->cfg.flags & PD_FLAG_NO_GRAPHS);
+  bool use_graph = (any_two || any_res) && !c->time_kernels && !(c->cfg.flags & PD_FLAG_NO_GRAPHS);
   if (use_graph) {
     std::string sig = std::to_string(K) + (any_check ? "c" : "n") + std::to_string(nslot_list) + ":" +
                       std::to_string(c->precision);
     for (auto& L : launches) {
-      if (L.resident) continue;
+      if (L.resident) {
+        sig += "|r" + std::to_string(L.nx) + "," + std::to_string(L.rv->team()) + "," +
+               std::to_string(L.rv->threads()) + "," + std::to_string(L.npairs) + "," + std::to_string(L.range_off) +
+               "," + std::to_string(L.nranges);
+        continue;
+      }
       sig += "|" + std::string(L.tv ? "tv" : "l1") + (L.z3 ? "z" + std::to_string(L.pz) + "," + std::to_string(L.zg) + "," +
                                                                 std::to_string(L.z_off) + "," + std::to_string(L.nzr)
                                                           : std::string()) +
@@ -1274,10 +1287,10 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     if (G.exec) {
       if ((e = step_err("graph launch", hipGraphLaunch(G.exec, c->stream))) != hipSuccess) return e;
       c->graph_replays++;
-    } else if ((e = step_err("two-launch kernels", enqueue_rest(false))) != hipSuccess) {
+    } else if ((e = step_err("step kernels", enqueue_rest(false))) != hipSuccess) {
       return e;
     }
-  } else if ((e = step_err("two-launch kernels", enqueue_rest(c->time_kernels))) != hipSuccess) {
+  } else if ((e = step_err("step kernels", enqueue_rest(c->time_kernels))) != hipSuccess) {
     return e;
   }
   return hipSuccess;

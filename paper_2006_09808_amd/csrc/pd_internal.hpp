@@ -168,7 +168,7 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // step condition and stop the volume (status 1 or 2) if it fails.
 hipError_t launch_tv_setup(const Vol* vols, Ctl* ctl, int slot, size_t npair_pts, int precision, hipStream_t st);
 
-// Resident (multi-iteration, cooperative) launch for square n x n slices.
+// Resident (multi-iteration, all workgroups co-resident) launch for square n x n slices.
 // resident_team(n) is the workgroups per pair (0: no resident kernel for n);
 // resident_max_teams(n) the teams that can be co-resident on the device.
 // Teams are placed one XCD apart (team t on XCD t mod 8), so a launch covers

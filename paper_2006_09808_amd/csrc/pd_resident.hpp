@@ -19,9 +19,13 @@
 // workgroups are not spread evenly over the XCDs, teams are formed from
 // workgroup indices instead and use agent-scope release/acquire fences (L2
 // write-back and invalidate) for every barrier, which is correct wherever
-// the workgroups run.  The launch is cooperative (every workgroup
-// co-resident); a bounded spin turns a barrier that never completes into an
-// abort flag that every workgroup sees, so the grid always drains.
+// the workgroups run.  The launch is an ordinary one sized to the device's
+// co-resident capacity (the occupancy calculator's workgroups per CU times
+// the CUs), so on an otherwise idle device every workgroup is resident at
+// once; a bounded spin turns a barrier that never completes (other work
+// holding CUs) into an abort flag that every workgroup sees, so the grid
+// always drains, and the host then reruns the requests on the two-launch
+// path.
 #pragma once
 
 #include "pd_kern_impl.hpp"
@@ -435,16 +439,18 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
     }
 }
 
-// Cooperative launch of `grid` workgroups (a multiple of TEAM).  Returns
-// hipErrorCooperativeLaunchTooLarge if they cannot all be co-resident.
+// Launch of `nteams` teams, rounded up to whole rounds of one team per XCD
+// (grid = a multiple of 8 TEAM workgroups; the padding teams exit at once).
+// The caller keeps nteams within resident_max_teams, the co-resident
+// capacity.
 template <int NX, int NY, int TEAM, int NT>
 hipError_t launch_resident_t(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                              unsigned* counters, int* abort_flag, int fenced, unsigned spin_limit, hipStream_t st) {
   const int rounds = (nteams + kXcds - 1) / kXcds;
   const int grid = rounds * kXcds * TEAM;
-  void* args[] = {(void*)&vols,     (void*)&ranges,     (void*)&nranges, (void*)&ctl,       (void*)&counters,
-                  (void*)&abort_flag, (void*)&nteams,   (void*)&fenced,  (void*)&spin_limit};
-  return hipLaunchCooperativeKernel((const void*)k_resident<NX, NY, TEAM, NT>, dim3(grid), dim3(NT), args, 0, st);
+  hipLaunchKernelGGL((k_resident<NX, NY, TEAM, NT>), dim3(grid), dim3(NT), 0, st, vols, ranges, nranges, ctl,
+                     counters, abort_flag, nteams, fenced, spin_limit);
+  return hipGetLastError();
 }
 
 template <int NX, int NY, int TEAM, int NT>

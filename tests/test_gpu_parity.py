@@ -386,11 +386,13 @@ def test_resident_protocols_and_two_launch_path_agree(solver, solver_two, solver
 
 
 @pytest.mark.parametrize("gap_tol", [0.0, 1e-9])
-def test_graph_replay_equals_eager(torch_mod, gap_tol):
-    """Steps of the two-launch path replayed from a captured HIP graph give the
-    eager result bitwise, on every replay, with eager work in between."""
+@pytest.mark.parametrize("ny,nx", [(96, 64), (128, 128)])
+def test_graph_replay_equals_eager(torch_mod, gap_tol, ny, nx):
+    """Steps replayed from a captured HIP graph give the eager result bitwise,
+    on every replay, with eager work in between: the two-launch path (96x64)
+    and the resident kernel (128x128, whose launches are captured too)."""
     import paper_2006_09808_amd as pd
-    w, delta = make_case(81, 5, 96, 64, lam=1e-3, max_iter=300, gap_tol=gap_tol, check_every=50)
+    w, delta = make_case(81, 5, ny, nx, lam=1e-3, max_iter=300, gap_tol=gap_tol, check_every=50)
     sp = w.solver_params()
     with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=50, graphs=False) as eager:
         ref, iref = gpu_solve(eager, torch_mod, delta, **sp)
