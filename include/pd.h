@@ -95,9 +95,10 @@ enum {
                                 they share an XCD                              */
   PD_FLAG_NO_GRAPHS = 8,     /* never replay a step of the two-launch path from
                                 a captured HIP graph                           */
-  PD_FLAG_TEST_BARRIER_GIVEUP = 16 /* test hook: resident-kernel team barriers
-                                poll only twice before they give up, which
-                                forces the recovery path below             */
+  PD_FLAG_TEST_BARRIER_GIVEUP = 16 /* test hook: resident-kernel barriers give
+                                up at their first wait (every workgroup exits
+                                before touching state), which forces the
+                                recovery path below                        */
 };
 /* Recovery from a resident launch that cannot complete.  The resident kernel
  * synchronises the workgroups of a team with bounded spin barriers; if its
@@ -137,7 +138,8 @@ typedef struct {
                           round length.                                          */
   int flags;           /* PD_FLAG_* */
   const char* tune_cache; /* path of a text file of autotuner choices, one line
-                          "nx ny variant rows cols" per slice shape: read at
+                          "nx ny variant rows cols plan_x plan_y" per slice
+                          shape (five-field lines read with plans 0): read at
                           pd_create if it exists (lines that pd_tune_set would
                           reject are skipped), rewritten after every pd_tune
                           and pd_tune_set.  NULL: the PD_TUNE_CACHE environment
@@ -288,33 +290,52 @@ pd_status pd_kernel_time_reset(pd_ctx* c);
 /* One timed configuration of a slice shape (pd_tune). */
 typedef struct {
   int nx, ny, nz, iters;  /* problem timed: nz slices of ny x nx, iters iterations   */
-  int path;               /* 0: resident kernel, 1: two launches per iteration       */
-  int variant;            /* resident: variant index; two-launch: -1                 */
+  int path;               /* 0: resident kernel (whole iterations); 1: column kernel
+                             of the two-launch path alone; 2: its row kernel alone */
+  int variant;            /* resident: variant index; otherwise -1                   */
   int team, threads;      /* resident: workgroups per slice pair, threads per group  */
-  int rows, cols;         /* two-launch: rows per row-kernel workgroup, columns per
-                             column-kernel workgroup; resident: 0                    */
+  int rows, cols;         /* row kernel: rows per workgroup; column kernel: columns
+                             per workgroup; 0 otherwise                             */
+  int plan;               /* column kernel: pass plan of the ny transforms; row
+                             kernel: of the nx transforms; resident: the variant's
+                             plan of both axes                                      */
   double ms;              /* best of three timed runs (HIP events), milliseconds      */
 } pd_tune_entry;
 
 /* Autotuner: time every kernel configuration of the nx x ny slice shape on a
- * zero-filled volume of nz slices for `iters` iterations (resident-kernel
- * variants for square FP32 shapes; row/column tile sizes of the two-launch
- * kernels), then make the fastest of each path the context's choice for that
- * shape.  Needs arena space like a solve of that size; blocks until done and
- * runs between scheduling rounds.  The choice is per shape, whatever the
- * slice count of later requests: the widest resident teams win for small
- * batches and lose for large ones, so tune with a representative nz.  Up to max_entries timings are written to
- * entries (may be NULL), their count to *n_entries.
+ * zero-filled volume of nz slices for `iters` iterations, then make the
+ * fastest of each kind the context's choice for that shape:
+ *   - resident-kernel variants (square FP32 shapes: workgroups per pair x
+ *     threads per workgroup x FFT pass plan);
+ *   - the two-launch path's column kernel per tile width and FFT pass plan of
+ *     the length-ny transforms, and its row kernel per tile height and pass
+ *     plan of the length-nx transforms, each timed alone.
+ * A pass plan is a factorisation of the transform length into the radices
+ * of its Stockham passes (256 as 16 x 16, 8 x 8 x 4 or 4 x 4 x 16; 384 as
+ * 16 x 24, 24 x 16 or 8 x 6 x 8; ...); FP32 transforms of a direct length
+ * over whole tiles have several, every other transform runs the default.
+ * Plans compute the same DFT with different rounding, so solves under
+ * different plans agree to rounding, not bit for bit (resident variants of
+ * one plan, and tile sizes, do agree bit for bit; a step that needs more
+ * co-resident teams than the chosen variant has switches only to a variant
+ * of the same plan).  Needs arena space like a solve of that
+ * size; blocks until done and runs between scheduling rounds.  The choice is
+ * per shape, whatever the slice count of later requests: the widest resident
+ * teams win for small batches and lose for large ones, so tune with a
+ * representative nz.  Up to max_entries timings are written to entries (may
+ * be NULL), their count to *n_entries.
  * Errors: PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_BUDGET, PD_ERR_HIP. */
 pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* entries, int max_entries,
                   int* n_entries);
 
 /* Set / read the context's configuration choice for the nx x ny shape
  * (e.g. a choice saved from an earlier pd_tune).  variant < 0, rows <= 0 or
- * cols <= 0 select the default of that knob; invalid values are rejected
- * with PD_ERR_ARG. */
-pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols);
-pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols);
+ * cols <= 0 select the default of that knob, plan_x / plan_y <= 0 the
+ * default pass plan of the row / column transforms; invalid values are
+ * rejected with PD_ERR_ARG.  A plan applies where it exists (FP32 whole-tile
+ * transforms of the L1 model's iterations); elsewhere the default runs. */
+pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols, int plan_x, int plan_y);
+pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols, int* plan_x, int* plan_y);
 
 /* Scheduling steps of the two-launch path captured into HIP graphs, and
  * steps replayed from one, since pd_create. */

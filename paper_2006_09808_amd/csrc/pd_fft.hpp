@@ -224,43 +224,84 @@ __device__ __forceinline__ void dft_ab(cpx<T>* x) {
 
 // ---------------------------------------------------------------------------
 // per-length pass plans (radices in inverse-transform order; the forward
-// transform runs them reversed)
+// transform runs them reversed).  Plan<N, 0> is the default of each length;
+// Plan<N, 1..> are alternative factorisations of the same length, among which
+// the autotuner chooses for the two-launch kernels.  Each plan computes the
+// same DFT; only the rounding and the speed differ.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int PV = 0>
 struct Plan;
-#define PD_PLAN(N_, M_, A_, B_, C_)                              \
+template <int N>
+struct PlanCount {
+  static constexpr int value = 1;
+};
+#define PD_PLAN(N_, PV_, M_, A_, B_, C_)                         \
   template <>                                                    \
-  struct Plan<N_> {                                              \
+  struct Plan<N_, PV_> {                                         \
     static constexpr int M = M_;                                 \
     static constexpr int r(int i) { return i == 0 ? A_ : i == 1 ? B_ : C_; } \
   };
-PD_PLAN(8, 1, 8, 1, 1)
-PD_PLAN(16, 1, 16, 1, 1)
-PD_PLAN(24, 2, 8, 3, 1)
-PD_PLAN(32, 2, 8, 4, 1)
-PD_PLAN(48, 2, 16, 3, 1)
-PD_PLAN(64, 2, 8, 8, 1)
-PD_PLAN(96, 2, 8, 12, 1)
-PD_PLAN(128, 2, 16, 8, 1)
-PD_PLAN(192, 2, 16, 12, 1)
-PD_PLAN(256, 2, 16, 16, 1)
-PD_PLAN(288, 2, 12, 24, 1)
-PD_PLAN(384, 2, 16, 24, 1)
-PD_PLAN(512, 3, 8, 8, 8)
-PD_PLAN(576, 2, 24, 24, 1)
-PD_PLAN(768, 3, 24, 8, 4)
+#define PD_PLAN_COUNT(N_, K_)                                    \
+  template <>                                                    \
+  struct PlanCount<N_> {                                         \
+    static constexpr int value = K_;                             \
+  };
+PD_PLAN(8, 0, 1, 8, 1, 1)
+PD_PLAN(16, 0, 1, 16, 1, 1)
+PD_PLAN(24, 0, 2, 8, 3, 1)
+PD_PLAN(32, 0, 2, 8, 4, 1)
+PD_PLAN(48, 0, 2, 16, 3, 1)
+PD_PLAN(64, 0, 2, 8, 8, 1)
+PD_PLAN(64, 1, 2, 16, 4, 1)
+PD_PLAN(64, 2, 2, 4, 16, 1)
+PD_PLAN_COUNT(64, 3)
+PD_PLAN(96, 0, 2, 8, 12, 1)
+PD_PLAN(96, 1, 2, 12, 8, 1)
+PD_PLAN(96, 2, 2, 24, 4, 1)
+PD_PLAN_COUNT(96, 3)
+PD_PLAN(128, 0, 2, 16, 8, 1)
+PD_PLAN(128, 1, 2, 8, 16, 1)
+PD_PLAN(128, 2, 3, 8, 4, 4)
+PD_PLAN_COUNT(128, 3)
+PD_PLAN(192, 0, 2, 16, 12, 1)
+PD_PLAN(192, 1, 2, 12, 16, 1)
+PD_PLAN(192, 2, 2, 24, 8, 1)
+PD_PLAN_COUNT(192, 3)
+PD_PLAN(256, 0, 2, 16, 16, 1)
+PD_PLAN(256, 1, 3, 8, 8, 4)
+PD_PLAN(256, 2, 3, 4, 4, 16)
+PD_PLAN_COUNT(256, 3)
+PD_PLAN(288, 0, 2, 12, 24, 1)
+PD_PLAN(288, 1, 2, 24, 12, 1)
+PD_PLAN_COUNT(288, 2)
+PD_PLAN(384, 0, 2, 16, 24, 1)
+PD_PLAN(384, 1, 2, 24, 16, 1)
+PD_PLAN(384, 2, 3, 8, 6, 8)
+PD_PLAN_COUNT(384, 3)
+PD_PLAN(512, 0, 3, 8, 8, 8)
+PD_PLAN(512, 1, 3, 16, 8, 4)
+PD_PLAN(512, 2, 3, 4, 8, 16)
+PD_PLAN_COUNT(512, 3)
+PD_PLAN(576, 0, 2, 24, 24, 1)
+PD_PLAN(576, 1, 3, 12, 8, 6)
+PD_PLAN_COUNT(576, 2)
+PD_PLAN(768, 0, 3, 24, 8, 4)
+PD_PLAN(768, 1, 3, 16, 8, 6)
+PD_PLAN(768, 2, 3, 12, 8, 8)
+PD_PLAN_COUNT(768, 3)
 #undef PD_PLAN
+#undef PD_PLAN_COUNT
 
 // radix of the i-th executed pass: inverse runs r(0..M-1), forward r(M-1..0)
-template <int N, int DIR>
+template <int N, int DIR, int PV = 0>
 constexpr int pass_radix(int i) {
-  return DIR > 0 ? Plan<N>::r(i) : Plan<N>::r(Plan<N>::M - 1 - i);
+  return DIR > 0 ? Plan<N, PV>::r(i) : Plan<N, PV>::r(Plan<N, PV>::M - 1 - i);
 }
 // product of the radices executed before pass i
-template <int N, int DIR>
+template <int N, int DIR, int PV = 0>
 constexpr int pass_prod(int i) {
   int p = 1;
-  for (int t = 0; t < i; ++t) p *= pass_radix<N, DIR>(t);
+  for (int t = 0; t < i; ++t) p *= pass_radix<N, DIR, PV>(t);
   return p;
 }
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
@@ -272,7 +313,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 // (rows, lds[s*LDN + n + n/32]).  Butterfly w of a pass with N/Q butterflies
 // per sequence belongs to thread w mod NT.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int S, int NT, bool COLS>
+template <typename T, int N, int S, int NT, bool COLS, int PV = 0>
 struct Fft {
   static constexpr int kNT = NT;
   static constexpr int LDN = N + N / 32 + 1;                 // padded row (rows layout)
@@ -328,10 +369,11 @@ struct Fft {
   // a pass after the first: read LDS, twiddle, DFT; if LAST keep the
   // outputs (positions j + r N/Q) in v, else write them back to LDS.
   template <int DIR, int PI, bool LAST>
-  static __device__ __forceinline__ void pass_from_lds(cpx<T> (&v)[nq<pass_radix<N, DIR>(PI)>()][pass_radix<N, DIR>(PI)],
-                                                       cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid) {
-    constexpr int Q = pass_radix<N, DIR>(PI);
-    constexpr int P = pass_prod<N, DIR>(PI);
+  static __device__ __forceinline__ void pass_from_lds(
+      cpx<T> (&v)[nq<pass_radix<N, DIR, PV>(PI)>()][pass_radix<N, DIR, PV>(PI)], cpx<T>* lds,
+      const cpx<T>* __restrict__ tw, int tid) {
+    constexpr int Q = pass_radix<N, DIR, PV>(PI);
+    constexpr int P = pass_prod<N, DIR, PV>(PI);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < nq<Q>(); ++q) {
@@ -362,11 +404,12 @@ struct Fft {
     }
   }
 
-  static constexpr int M = Plan<N>::M;
+  static constexpr int M = Plan<N, PV>::M;
+  static_assert(pass_prod<N, -1, PV>(Plan<N, PV>::M) == N, "the pass radices of a plan multiply to its length");
   template <int DIR>
-  static constexpr int QF() { return pass_radix<N, DIR>(0); }
+  static constexpr int QF() { return pass_radix<N, DIR, PV>(0); }
   template <int DIR>
-  static constexpr int QL() { return pass_radix<N, DIR>(M - 1); }
+  static constexpr int QL() { return pass_radix<N, DIR, PV>(M - 1); }
 
   // Whole transform: `in` holds the inputs of the first pass (positions
   // j + r N/QF), `out` receives the outputs of the last pass (positions
@@ -392,7 +435,7 @@ struct Fft {
     } else {
       first_to_lds<DIR, QF<DIR>()>(in, lds, tid);
       if constexpr (M == 3) {
-        constexpr int Q1 = pass_radix<N, DIR>(1);
+        constexpr int Q1 = pass_radix<N, DIR, PV>(1);
         cpx<T> mid[nq<Q1>()][Q1];
         pass_from_lds<DIR, 1, false>(mid, lds, tw, tid);
       }
@@ -491,9 +534,10 @@ struct Blue {
   static __device__ __forceinline__ void sync_before_reuse() { __syncthreads(); }
 };
 
-// Engine of a kernel's transform axis: EXT < 2 the plain length-N engine,
-// EXT == 2 the Bluestein engine on length-N transforms.
-template <typename T, int N, int S, int NT, bool COLS, int EXT>
-using AxisFft = std::conditional_t<EXT == 2, Blue<T, N, S, NT, COLS>, Fft<T, N, S, NT, COLS>>;
+// Engine of a kernel's transform axis: EXT < 2 the plain length-N engine with
+// pass plan PV, EXT == 2 the Bluestein engine on length-N transforms (default
+// plan).
+template <typename T, int N, int S, int NT, bool COLS, int EXT, int PV = 0>
+using AxisFft = std::conditional_t<EXT == 2, Blue<T, N, S, NT, COLS>, Fft<T, N, S, NT, COLS, PV>>;
 
 }  // namespace pdk

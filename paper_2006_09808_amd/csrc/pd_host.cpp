@@ -509,6 +509,7 @@ struct pd_ctx {
   struct Tuned {
     int res_variant = 0;
     int rows = 0, cols = 0;
+    int plan_x = 0, plan_y = 0;   // pass plans of the row (nx) and column (ny) transforms
   };
   std::map<std::pair<int, int>, Tuned> tuned;
   std::string tune_cache;      // file of the choices ("" = none)
@@ -954,6 +955,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     bool resident;
     bool tv;                                 // weighted TV model (four launches per iteration)
     int px, py, er, ec;                      // transform lengths and kernel variants (row, column)
+    int planx, plany;                        // pass plans of the row and column transforms
     bool z3;                                 // 3-D kernel: planes plus the z view
     int pz, ez, zg, z_off, nzr;              // z: transform length, variant, groups per volume, ranges
     int team;
@@ -982,13 +984,15 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     if (rv) {
       // the chosen variant was timed at some slice count; when this step's
       // pairs need more than one of its co-resident launches, take the
-      // variant with the most co-resident teams instead (all variants give
-      // the same bits)
+      // variant of the same FFT plan with the most co-resident teams instead
+      // (variants of one plan give the same bits, so a request's iterates do
+      // not depend on the other requests of the step)
       int npairs = 0;
       for (Job* j : g.second) npairs += j->L.P;
       if (npairs > maxt)
         for (int v = 0; v < resident_variant_count(nx); ++v) {
           const ResidentVariant* cand = resident_variant(nx, v);
+          if (cand->plan() != rv->plan()) continue;
           const int m = std::min(cand->max_teams(), kMaxTeamSlots);
           if (m > maxt) {
             rv = cand;
@@ -1040,6 +1044,11 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       L.py = axis_phys(ny);
       L.er = axis_ext(nx, ny, L.rows);
       L.ec = axis_ext(ny, nx, L.cols);
+      // a tuned pass plan applies to FP32 whole-tile transforms of the L1
+      // iteration; everything else runs the default plan
+      const bool plain = c->precision == PD_FP32 && !tv && !z3;
+      L.planx = (plain && L.er == 0 && tn.plan_x < plan_count(nx)) ? tn.plan_x : 0;
+      L.plany = (plain && L.ec == 0 && tn.plan_y < plan_count(ny)) ? tn.plan_y : 0;
       for (Job* j : g.second) {
         Vol& V = c->h_vols[j->slot];
         V.row_groups = L.rg;
@@ -1157,12 +1166,12 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
           const Range* rcol = c->d_ranges + L.col_off;
           double pts = (double)L.npairs * L.nx * L.ny;
           auto col = [&] {
-            return launch_col(L.py, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
-                              it, c->precision, L.ec, c->stream);
+            return launch_col_p(L.py, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, L.plany, c->stream);
           };
           auto row = [&] {
-            return launch_row(L.px, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
-                              it, c->precision, L.er, c->stream);
+            return launch_row_p(L.px, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                                it, c->precision, L.er, L.planx, c->stream);
           };
           if (L.z3) {   // 3-D kernel: F_y, (F_z, dual prox, F_z^-1) on the z view, F_y^-1, row kernel
             const Range* rz = c->d_ranges + L.z_off;
@@ -1227,8 +1236,8 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
             if (r != hipSuccess) return r;
             continue;
           }
-          r = launch_col(L.py, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
-                         K - 1, c->precision, L.ec, c->stream);
+          r = launch_col_p(L.py, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                           K - 1, c->precision, L.ec, L.plany, c->stream);
           if (r != hipSuccess) return r;
         }
       }
@@ -1256,7 +1265,8 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
                                                           : std::string()) +
              std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
              std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
-             std::to_string(L.row_off) + "," + std::to_string(L.col_off);
+             std::to_string(L.row_off) + "," + std::to_string(L.col_off) + "," + std::to_string(L.planx) + "," +
+             std::to_string(L.plany);
     }
     auto& G = c->graphs[sig];
     G.last_use = ++c->graph_clock;
@@ -1498,11 +1508,16 @@ void worker_main(pd_ctx* c) {
 }
 
 // The checks pd_tune_set applies to one choice.
-pd_status tune_choice_check(const pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
+pd_status tune_choice_check(const pd_ctx* c, int nx, int ny, int variant, int rows, int cols, int plan_x,
+                            int plan_y) {
   if (!axis_ok(nx) || !axis_ok(ny)) return PD_ERR_SIZE;
   if (variant >= 0 && !(nx == ny && variant < resident_variant_count(nx))) return PD_ERR_ARG;
   if (rows > 0 && !rows_valid(rows, nx, ny, c->precision)) return PD_ERR_ARG;
   if (cols > 0 && !cols_valid(cols, nx, ny, c->precision)) return PD_ERR_ARG;
+  // alternative plans exist for FP32 direct lengths only
+  const int px_max = (c->precision == PD_FP32 && !axis_blue(nx)) ? plan_count(nx) : 1;
+  const int py_max = (c->precision == PD_FP32 && !axis_blue(ny)) ? plan_count(ny) : 1;
+  if (plan_x >= px_max || plan_y >= py_max) return PD_ERR_ARG;
   return PD_OK;
 }
 
@@ -1515,13 +1530,16 @@ void load_tune_cache(pd_ctx* c) {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof line, f)) {
-    int nx, ny, v, r, cl;
-    if (std::sscanf(line, "%d %d %d %d %d", &nx, &ny, &v, &r, &cl) != 5) continue;
-    if (tune_choice_check(c, nx, ny, v, r, cl) != PD_OK) continue;
+    int nx, ny, v, r, cl, px = 0, py = 0;
+    const int got = std::sscanf(line, "%d %d %d %d %d %d %d", &nx, &ny, &v, &r, &cl, &px, &py);
+    if (got != 5 && got != 7) continue;   // five fields: a file written before pass plans were tuned
+    if (tune_choice_check(c, nx, ny, v, r, cl, px < 0 ? 0 : px, py < 0 ? 0 : py) != PD_OK) continue;
     pd_ctx::Tuned tn;
     tn.res_variant = v >= 0 ? v : 0;
     tn.rows = r > 0 ? r : 0;
     tn.cols = cl > 0 ? cl : 0;
+    tn.plan_x = px > 0 ? px : 0;
+    tn.plan_y = py > 0 ? py : 0;
     c->tuned[{nx, ny}] = tn;
   }
   std::fclose(f);
@@ -1537,7 +1555,8 @@ void save_tune_cache(const pd_ctx* c) {
     const int nx = kv.first.first, ny = kv.first.second;
     // as pd_tune_get reports it: no resident variant for other shapes
     const int v = (nx == ny && resident_variant_count(nx) > 0) ? kv.second.res_variant : -1;
-    ok &= std::fprintf(f, "%d %d %d %d %d\n", nx, ny, v, kv.second.rows, kv.second.cols) > 0;
+    ok &= std::fprintf(f, "%d %d %d %d %d %d %d\n", nx, ny, v, kv.second.rows, kv.second.cols, kv.second.plan_x,
+                       kv.second.plan_y) > 0;
   }
   ok &= std::fclose(f) == 0;
   if (ok) std::rename(tmp.c_str(), c->tune_cache.c_str());
@@ -1729,7 +1748,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
   c->precision = cfg->precision;
   c->nslots = cfg->max_slots > 0 ? cfg->max_slots : kDefaultSlots;
   c->time_kernels = (cfg->flags & PD_FLAG_TIME_KERNELS) != 0;
-  if (cfg->flags & PD_FLAG_TEST_BARRIER_GIVEUP) c->spin_limit = 2;
+  if (cfg->flags & PD_FLAG_TEST_BARRIER_GIVEUP) c->spin_limit = 0;
   if (cfg->tune_cache) c->tune_cache = cfg->tune_cache;
   else if (const char* env = std::getenv("PD_TUNE_CACHE")) c->tune_cache = env;
   c->cfg.tune_cache = nullptr;   // the caller's string is not kept
@@ -2015,36 +2034,57 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
           continue;
         }
         // time per iteration of all P pairs (nteams pairs per launch)
-        pd_tune_entry t{nx, ny, nz, iters, 0, v, rv->team(), rv->threads(), 0, 0, best * (double)P / nteams};
+        pd_tune_entry t{nx, ny, nz, iters, 0, v, rv->team(), rv->threads(), 0, 0, rv->plan(),
+                        best * (double)P / nteams};
         all.push_back(t);
       }
     }
-    // two-launch tile sizes
-    for (int rows : {8, row_group_big(nx)}) {
+    // two-launch path: the column kernel per tile width and pass plan of the
+    // column (ny) transforms, the row kernel per tile height and pass plan of
+    // the row (nx) transforms, each timed alone (the two choices are
+    // independent; an iteration runs one of each)
+    const int rg0 = ceil_div(ny, rows_per_wg(nx, ny, c->precision));
+    const int cg0 = ceil_div(nx, cols_per_wg(nx, ny, c->precision));
+    for (int cols : {8, 16}) {
       if (e != hipSuccess) break;
-      if (!rows_valid(rows, nx, ny, c->precision)) continue;
-      for (int cols : {8, 16}) {
-        if (e != hipSuccess) break;
-        if (!cols_valid(cols, nx, ny, c->precision)) continue;
-        bool dup = false;
-        for (auto& t : all) dup |= t.path == 1 && t.rows == rows && t.cols == cols;
-        if (dup) continue;
-        int rg = ceil_div(ny, rows), cg = ceil_div(nx, cols);
-        const int er = axis_ext(nx, ny, rows), ec = axis_ext(ny, nx, cols);
-        if ((e = upload_vol(rg, cg)) != hipSuccess) break;
+      if (!cols_valid(cols, nx, ny, c->precision)) continue;
+      const int cg = ceil_div(nx, cols);
+      const int ec = axis_ext(ny, nx, cols);
+      const int nplans = (c->precision == PD_FP32 && ec == 0) ? plan_count(ny) : 1;
+      for (int plan = 0; plan < nplans && e == hipSuccess; ++plan) {
+        if ((e = upload_vol(rg0, cg)) != hipSuccess) break;
         double best = 0;
         e = time_it([&] {
           hipError_t r2 = hipSuccess;
-          for (int it = 0; it < iters && r2 == hipSuccess; ++it) {
-            r2 = launch_col(axis_phys(ny), COL_ITER, cols, P * cg, cg, c->d_vols, dr, 1, c->d_ctl, it, c->precision,
-                            ec, c->stream);
-            if (r2 == hipSuccess)
-              r2 = launch_row(axis_phys(nx), ROW_ITER, rows, P * rg, rg, c->d_vols, dr, 1, c->d_ctl, it,
-                              c->precision, er, c->stream);
-          }
+          for (int it = 0; it < iters && r2 == hipSuccess; ++it)
+            r2 = launch_col_p(axis_phys(ny), COL_ITER, cols, P * cg, cg, c->d_vols, dr, 1, c->d_ctl, it, c->precision,
+                              ec, plan, c->stream);
           return r2;
         }, &best);
-        pd_tune_entry t{nx, ny, nz, iters, 1, -1, 0, 0, rows, cols, best};
+        pd_tune_entry t{nx, ny, nz, iters, 1, -1, 0, 0, 0, cols, plan, best};
+        all.push_back(t);
+      }
+    }
+    for (int rows : {8, row_group_big(nx)}) {
+      if (e != hipSuccess) break;
+      if (!rows_valid(rows, nx, ny, c->precision)) continue;
+      bool dup = false;
+      for (auto& t : all) dup |= t.path == 2 && t.rows == rows;
+      if (dup) continue;
+      const int rg = ceil_div(ny, rows);
+      const int er = axis_ext(nx, ny, rows);
+      const int nplans = (c->precision == PD_FP32 && er == 0) ? plan_count(nx) : 1;
+      for (int plan = 0; plan < nplans && e == hipSuccess; ++plan) {
+        if ((e = upload_vol(rg, cg0)) != hipSuccess) break;
+        double best = 0;
+        e = time_it([&] {
+          hipError_t r2 = hipSuccess;
+          for (int it = 0; it < iters && r2 == hipSuccess; ++it)
+            r2 = launch_row_p(axis_phys(nx), ROW_ITER, rows, P * rg, rg, c->d_vols, dr, 1, c->d_ctl, it,
+                              c->precision, er, plan, c->stream);
+          return r2;
+        }, &best);
+        pd_tune_entry t{nx, ny, nz, iters, 2, -1, 0, 0, rows, 0, plan, best};
         all.push_back(t);
       }
     }
@@ -2061,16 +2101,21 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
     return PD_ERR_HIP;
   }
   pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
-  double best_res = 1e300, best_two = 1e300;
+  double best_res = 1e300, best_col = 1e300, best_row = 1e300;
   for (auto& t : all) {
     if (t.path == 0 && t.ms < best_res) {
       best_res = t.ms;
       tn.res_variant = t.variant;
     }
-    if (t.path == 1 && t.ms < best_two) {
-      best_two = t.ms;
-      tn.rows = t.rows;
+    if (t.path == 1 && t.ms < best_col) {
+      best_col = t.ms;
       tn.cols = t.cols;
+      tn.plan_y = t.plan;
+    }
+    if (t.path == 2 && t.ms < best_row) {
+      best_row = t.ms;
+      tn.rows = t.rows;
+      tn.plan_x = t.plan;
     }
   }
   c->tuned[{nx, ny}] = tn;
@@ -2084,11 +2129,11 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
   return PD_OK;
 }
 
-pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols) {
+pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols, int plan_x, int plan_y) {
   if (!c) return PD_ERR_ARG;
   CallGuard guard(c);
   if (!guard.ok) return PD_ERR_CANCELLED;
-  pd_status st = tune_choice_check(c, nx, ny, variant, rows, cols);
+  pd_status st = tune_choice_check(c, nx, ny, variant, rows, cols, plan_x < 0 ? 0 : plan_x, plan_y < 0 ? 0 : plan_y);
   if (st != PD_OK) return st;
   std::lock_guard<std::mutex> ex(c->exec_mu);   // between scheduling steps
   std::lock_guard<std::mutex> lk(c->mu);
@@ -2097,12 +2142,14 @@ pd_status pd_tune_set(pd_ctx* c, int nx, int ny, int variant, int rows, int cols
   tn.res_variant = variant >= 0 ? variant : 0;
   tn.rows = rows > 0 ? rows : 0;
   tn.cols = cols > 0 ? cols : 0;
+  tn.plan_x = plan_x > 0 ? plan_x : 0;
+  tn.plan_y = plan_y > 0 ? plan_y : 0;
   c->tuned[{nx, ny}] = tn;
   save_tune_cache(c);
   return PD_OK;
 }
 
-pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols) {
+pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* cols, int* plan_x, int* plan_y) {
   if (!c) return PD_ERR_ARG;
   CallGuard guard(c);
   if (!guard.ok) return PD_ERR_CANCELLED;
@@ -2111,6 +2158,8 @@ pd_status pd_tune_get(pd_ctx* c, int nx, int ny, int* variant, int* rows, int* c
   if (variant) *variant = (nx == ny && resident_variant_count(nx) > 0) ? tn.res_variant : -1;
   if (rows) *rows = tn.rows > 0 ? tn.rows : rows_per_wg(nx, ny, c->precision);
   if (cols) *cols = tn.cols > 0 ? tn.cols : cols_per_wg(nx, ny, c->precision);
+  if (plan_x) *plan_x = tn.plan_x;
+  if (plan_y) *plan_y = tn.plan_y;
   return PD_OK;
 }
 

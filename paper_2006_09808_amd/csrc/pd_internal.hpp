@@ -158,6 +158,14 @@ hipError_t launch_col(int n, int mode, int cols, int grid, int groups, const Vol
                       const Range* ranges, int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st);
 hipError_t launch_row(int n, int mode, int rows, int grid, int groups, const Vol* vols,
                       const Range* ranges, int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st);
+// The same with pass plan `plan` of length n (0 .. plan_count(n) - 1; plans
+// other than 0 for FP32 whole-tile transforms only).
+hipError_t launch_col_p(int n, int mode, int cols, int grid, int groups, const Vol* vols, const Range* ranges,
+                        int nranges, Ctl* ctl, int it, int precision, int ext, int plan, hipStream_t st);
+hipError_t launch_row_p(int n, int mode, int rows, int grid, int groups, const Vol* vols, const Range* ranges,
+                        int nranges, Ctl* ctl, int it, int precision, int ext, int plan, hipStream_t st);
+// Number of pass plans of a direct transform length (1 for any other n).
+int plan_count(int n);
 hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl, int it,
                          int precision, hipStream_t st);
 hipError_t launch_store_chi(const Vol* vols, int slot, size_t npairs_pts, int precision,
@@ -198,6 +206,7 @@ struct ResidentVariant {
   int (*max_teams)();
   int (*team)();
   int (*threads)();
+  int (*plan)();      // FFT pass plan of both axes (variants of one plan give the same bits)
 };
 // The library's fixed device scratch (pd_scratch.hip): device address of
 // `device`'s copy (the device must be current), and the lock that

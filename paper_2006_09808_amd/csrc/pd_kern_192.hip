@@ -3,5 +3,5 @@
 // 12 x 256 threads, 24 x 128 threads).
 #include "pd_resident.hpp"
 PD_INSTANTIATE(192)
-PD_INSTANTIATE_RESIDENT(192, 0, 12, 256)
-PD_INSTANTIATE_RESIDENT(192, 1, 24, 128)
+PD_INSTANTIATE_RESIDENT(192, 0, 12, 256, 0)
+PD_INSTANTIATE_RESIDENT(192, 1, 24, 128, 0)

@@ -66,11 +66,11 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV], int tid) {
 // EXT = 2: columns of any length ny <= (NY + 1) / 2 through the Bluestein
 //          engine on length-NY transforms; the last strip may be partial.
 // ---------------------------------------------------------------------------
-template <typename T, int NY, int S, int MODE, int EXT>
+template <typename T, int NY, int S, int MODE, int EXT, int PV = 0>
 __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
                                                   const Range* __restrict__ ranges, int nranges,
                                                   Ctl* __restrict__ ctl, int groups, int it) {
-  using F = AxisFft<T, NY, S, kThreads, true, EXT>;
+  using F = AxisFft<T, NY, S, kThreads, true, EXT, PV>;
   constexpr int QA = F::template QF<-1>();  // forward first radix == inverse last radix
   constexpr int QB = F::template QL<-1>();  // forward last radix == inverse first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
@@ -280,11 +280,11 @@ __global__ __launch_bounds__(kThreads) void k_col(const Vol* __restrict__ vols,
 // ---------------------------------------------------------------------------
 // EXT as for the column kernel, along rows: 1 = the last row group may be
 // partial, 2 = rows of any length nx <= (NX + 1) / 2 through Bluestein.
-template <typename T, int NX, int S, int MODE, int EXT>
+template <typename T, int NX, int S, int MODE, int EXT, int PV = 0>
 __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
                                                   const Range* __restrict__ ranges, int nranges,
                                                   Ctl* __restrict__ ctl, int groups, int it) {
-  using F = AxisFft<T, NX, S, kThreads, false, EXT>;
+  using F = AxisFft<T, NX, S, kThreads, false, EXT, PV>;
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
   __shared__ cpx<T> lds[F::LDS_ELEMS];
@@ -523,6 +523,50 @@ hipError_t launch_row_x(int ext, int mode, int grid, int groups, const Vol* vols
   }
 }
 
+// The iteration and check launches of FP32 whole-tile transforms with pass
+// plan PV > 0 (the autotuner's alternatives); every other mode runs the
+// default plan (a different plan computes the same DFT).
+template <int N, int S, int PV>
+hipError_t launch_col_pv(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                         int it, hipStream_t st) {
+  dim3 gr(grid), bl(kThreads);
+  switch (mode) {
+    case COL_ITER: hipLaunchKernelGGL((k_col<float, N, S, COL_ITER, 0, PV>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case COL_CHECK: hipLaunchKernelGGL((k_col<float, N, S, COL_CHECK, 0, PV>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    default: return launch_col_t<N, float, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  }
+  return hipGetLastError();
+}
+template <int N, int S, int PV>
+hipError_t launch_row_pv(int mode, int grid, int groups, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
+                         int it, hipStream_t st) {
+  if (mode != ROW_ITER) return launch_row_t<N, float, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  hipLaunchKernelGGL((k_row<float, N, S, ROW_ITER, 0, PV>), dim3(grid), dim3(kThreads), 0, st, vols, ranges, nranges,
+                     ctl, groups, it);
+  return hipGetLastError();
+}
+// plan index from a runtime value (0 .. PlanCount<N> - 1)
+template <int N, int S>
+hipError_t launch_col_plan(int plan, int mode, int grid, int groups, const Vol* vols, const Range* ranges,
+                           int nranges, Ctl* ctl, int it, hipStream_t st) {
+  if constexpr (PlanCount<N>::value > 1)
+    if (plan == 1) return launch_col_pv<N, S, 1>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  if constexpr (PlanCount<N>::value > 2)
+    if (plan == 2) return launch_col_pv<N, S, 2>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  if (plan != 0) return hipErrorInvalidValue;
+  return launch_col_t<N, float, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+}
+template <int N, int S>
+hipError_t launch_row_plan(int plan, int mode, int grid, int groups, const Vol* vols, const Range* ranges,
+                           int nranges, Ctl* ctl, int it, hipStream_t st) {
+  if constexpr (PlanCount<N>::value > 1)
+    if (plan == 1) return launch_row_pv<N, S, 1>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  if constexpr (PlanCount<N>::value > 2)
+    if (plan == 2) return launch_row_pv<N, S, 2>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+  if (plan != 0) return hipErrorInvalidValue;
+  return launch_row_t<N, float, S, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st);
+}
+
 // rows per row-kernel workgroup for length-N rows (FP32): the largest power
 // of two with at most 4096 points per workgroup, clamped to [8, 64]
 constexpr int row_s_big(int n) {
@@ -535,31 +579,41 @@ constexpr int row_s_big(int n) {
 
 // Defines launch_col_<N> / launch_row_<N>: transforms of length N, tile
 // width `cols` / `rows`, EXT `ext` (0: plain; 1: partial last tile; 2:
-// Bluestein transforms of any length <= (N + 1) / 2 on length-N transforms).
-// FP32 EXT 0 has two tile sizes; every other combination uses tiles of 8.
+// Bluestein transforms of any length <= (N + 1) / 2 on length-N transforms),
+// pass plan `plan` (FP32 whole tiles only; 0 elsewhere).  FP32 EXT 0 has two
+// tile sizes; every other combination uses tiles of 8.
 #define PD_INSTANTIATE(N)                                                                         \
   namespace pdk {                                                                                 \
   hipError_t launch_col_##N(int mode, int cols, int grid, int groups, const Vol* vols,            \
                             const Range* ranges, int nranges, Ctl* ctl, int it, int precision,    \
-                            int ext, hipStream_t st) {                                            \
+                            int ext, int plan, hipStream_t st) {                                  \
+    if (plan < 0 || plan >= PlanCount<N>::value || (plan != 0 && (precision == 1 || ext != 0)))    \
+      return hipErrorInvalidValue;                                                                \
     if (precision == 1) {                                                                         \
       if (cols != 8) return hipErrorInvalidValue;                                                 \
       return launch_col_x<N, double, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     }                                                                                             \
     if (ext == 0 && cols == 16 && N <= 512)                                                       \
-      return launch_col_t<N, float, (N <= 512 ? 16 : 8), 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+      return launch_col_plan<N, (N <= 512 ? 16 : 8)>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (ext == 0 && cols == 8)                                                                    \
+      return launch_col_plan<N, 8>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     if (cols == 8) return launch_col_x<N, float, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     return hipErrorInvalidValue;                                                                  \
   }                                                                                               \
   hipError_t launch_row_##N(int mode, int rows, int grid, int groups, const Vol* vols,            \
                             const Range* ranges, int nranges, Ctl* ctl, int it, int precision,    \
-                            int ext, hipStream_t st) {                                            \
+                            int ext, int plan, hipStream_t st) {                                  \
+    if (plan < 0 || plan >= PlanCount<N>::value || (plan != 0 && (precision == 1 || ext != 0)))    \
+      return hipErrorInvalidValue;                                                                \
     if (precision == 1) {                                                                         \
       if (rows != 8) return hipErrorInvalidValue;                                                 \
       return launch_row_x<N, double, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     }                                                                                             \
     constexpr int SB = row_s_big(N);                                                              \
-    if (ext == 0 && rows == SB) return launch_row_t<N, float, SB, 0>(mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (ext == 0 && rows == SB)                                                                   \
+      return launch_row_plan<N, SB>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    if (ext == 0 && rows == 8)                                                                    \
+      return launch_row_plan<N, 8>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     if (rows == 8) return launch_row_x<N, float, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     return hipErrorInvalidValue;                                                                  \
   }                                                                                               \

@@ -6,8 +6,8 @@
 namespace pdk {
 
 #define PD_DECL(N)                                                                                   \
-  hipError_t launch_col_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, hipStream_t); \
-  hipError_t launch_row_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, hipStream_t);
+  hipError_t launch_col_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, int, hipStream_t); \
+  hipError_t launch_row_##N(int, int, int, int, const Vol*, const Range*, int, Ctl*, int, int, int, int, hipStream_t);
 PD_DECL(8)
 PD_DECL(16)
 PD_DECL(24)
@@ -30,13 +30,17 @@ PD_DECL(768)
                                        unsigned, hipStream_t);                                           \
   int resident_max_teams_##N##_##V();                                                                    \
   int resident_team_##N##_##V();                                                                         \
-  int resident_threads_##N##_##V();
-#define PD_RES_LIST(X) X(64, 0) X(64, 1) X(64, 2) X(128, 0) X(128, 1) X(128, 2) X(192, 0) X(192, 1) X(256, 0) X(256, 1) X(256, 2)
+  int resident_threads_##N##_##V();                                                                      \
+  int resident_plan_##N##_##V();
+#define PD_RES_LIST(X)                                                                                  \
+  X(64, 0) X(64, 1) X(64, 2) X(128, 0) X(128, 1) X(128, 2) X(128, 3) X(192, 0) X(192, 1)    \
+  X(256, 0) X(256, 1) X(256, 2) X(256, 3)
 PD_RES_LIST(PD_DECL_RES)
 #undef PD_DECL_RES
 
 #define PD_RES_ENTRY(N, V) \
-  {N, launch_resident_##N##_##V, resident_max_teams_##N##_##V, resident_team_##N##_##V, resident_threads_##N##_##V},
+  {N, launch_resident_##N##_##V, resident_max_teams_##N##_##V, resident_team_##N##_##V, resident_threads_##N##_##V, \
+   resident_plan_##N##_##V},
 static const ResidentVariant kResident[] = {PD_RES_LIST(PD_RES_ENTRY)};
 #undef PD_RES_ENTRY
 #undef PD_RES_LIST
@@ -73,10 +77,10 @@ int blue_len(int n) {
 }
 
 #define PD_CASE(N, KIND) \
-  case N: return launch_##KIND##_##N(mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, st);
+  case N: return launch_##KIND##_##N(mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, plan, st);
 
-hipError_t launch_col(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
-                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+hipError_t launch_col_p(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
+                        int nranges, Ctl* ctl, int it, int precision, int ext, int plan, hipStream_t st) {
   switch (n) {
     PD_CASE(8, col) PD_CASE(16, col) PD_CASE(24, col) PD_CASE(32, col) PD_CASE(48, col)
     PD_CASE(64, col) PD_CASE(96, col) PD_CASE(128, col) PD_CASE(192, col) PD_CASE(256, col)
@@ -85,13 +89,44 @@ hipError_t launch_col(int n, int mode, int g, int grid, int groups, const Vol* v
   }
 }
 
-hipError_t launch_row(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
-                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+hipError_t launch_row_p(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
+                        int nranges, Ctl* ctl, int it, int precision, int ext, int plan, hipStream_t st) {
   switch (n) {
     PD_CASE(8, row) PD_CASE(16, row) PD_CASE(24, row) PD_CASE(32, row) PD_CASE(48, row)
     PD_CASE(64, row) PD_CASE(96, row) PD_CASE(128, row) PD_CASE(192, row) PD_CASE(256, row)
     PD_CASE(288, row) PD_CASE(384, row) PD_CASE(512, row) PD_CASE(576, row) PD_CASE(768, row)
     default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+  return launch_col_p(n, mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, 0, st);
+}
+
+hipError_t launch_row(int n, int mode, int g, int grid, int groups, const Vol* vols, const Range* ranges,
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+  return launch_row_p(n, mode, g, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, 0, st);
+}
+
+int plan_count(int n) {
+  switch (n) {
+    case 8: return PlanCount<8>::value;
+    case 16: return PlanCount<16>::value;
+    case 24: return PlanCount<24>::value;
+    case 32: return PlanCount<32>::value;
+    case 48: return PlanCount<48>::value;
+    case 64: return PlanCount<64>::value;
+    case 96: return PlanCount<96>::value;
+    case 128: return PlanCount<128>::value;
+    case 192: return PlanCount<192>::value;
+    case 256: return PlanCount<256>::value;
+    case 288: return PlanCount<288>::value;
+    case 384: return PlanCount<384>::value;
+    case 512: return PlanCount<512>::value;
+    case 576: return PlanCount<576>::value;
+    case 768: return PlanCount<768>::value;
+    default: return 1;
   }
 }
 #undef PD_CASE

@@ -67,9 +67,15 @@ struct ExAddr {
 };
 
 // Arrive at a team barrier and wait for `target` arrivals in total; thread 0
-// only.  Returns false once the spin limit is hit or another workgroup aborted.
+// only.  Returns false once the spin limit is hit or another workgroup
+// aborted.  A spin limit of 0 gives up at once (a host-set test of the
+// recovery path).
 __device__ __forceinline__ bool arrive_wait(unsigned* cnt, unsigned add, unsigned target, unsigned mask,
                                             unsigned* seen, int* abort_flag, unsigned spin_limit) {
+  if (spin_limit == 0) {
+    __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
   unsigned v = __hip_atomic_fetch_add(cnt, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
   unsigned spins = 0;
   while ((v & mask) < target) {
@@ -107,12 +113,12 @@ __device__ __forceinline__ bool team_barrier(unsigned* cnt, unsigned target, int
   return *lds_flag != 0;
 }
 
-template <int NX, int NY, int TEAM, int NT>
+template <int NX, int NY, int TEAM, int NT, int PV>
 struct Resident {
   static constexpr int RT = NY / TEAM;   // rows per workgroup (row phase)
   static constexpr int CT = NX / TEAM;   // columns per workgroup (column phase)
-  using FR = Fft<float, NX, RT, NT, false>;
-  using FC = Fft<float, NY, CT, NT, true>;
+  using FR = Fft<float, NX, RT, NT, false, PV>;   // PV: FFT pass plan of both axes
+  using FC = Fft<float, NY, CT, NT, true, PV>;
   static constexpr int LDS = FR::LDS_ELEMS > FC::LDS_ELEMS ? FR::LDS_ELEMS : FC::LDS_ELEMS;
   // row phase: inverse first radix QI (exchange in), inverse last radix QO
   // (chi state; forward first radix)
@@ -131,12 +137,12 @@ struct Resident {
 // counters: one barrier counter per team slot, then kXcds per-XCD tickets and
 // the grid arrival counter, kCounterStride words apart; zeroed before every
 // launch.
-template <int NX, int NY, int TEAM, int NT>
+template <int NX, int NY, int TEAM, int NT, int PV>
 __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
                                                  int* __restrict__ abort_flag, int nteams, int force_fenced,
                                                  unsigned spin_limit) {
-  using R = Resident<NX, NY, TEAM, NT>;
+  using R = Resident<NX, NY, TEAM, NT, PV>;
   using FR = typename R::FR;
   using FC = typename R::FC;
   using T = float;
@@ -443,22 +449,22 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
 // (grid = a multiple of 8 TEAM workgroups; the padding teams exit at once).
 // The caller keeps nteams within resident_max_teams, the co-resident
 // capacity.
-template <int NX, int NY, int TEAM, int NT>
+template <int NX, int NY, int TEAM, int NT, int PV>
 hipError_t launch_resident_t(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                              unsigned* counters, int* abort_flag, int fenced, unsigned spin_limit, hipStream_t st) {
   const int rounds = (nteams + kXcds - 1) / kXcds;
   const int grid = rounds * kXcds * TEAM;
-  hipLaunchKernelGGL((k_resident<NX, NY, TEAM, NT>), dim3(grid), dim3(NT), 0, st, vols, ranges, nranges, ctl,
+  hipLaunchKernelGGL((k_resident<NX, NY, TEAM, NT, PV>), dim3(grid), dim3(NT), 0, st, vols, ranges, nranges, ctl,
                      counters, abort_flag, nteams, fenced, spin_limit);
   return hipGetLastError();
 }
 
-template <int NX, int NY, int TEAM, int NT>
+template <int NX, int NY, int TEAM, int NT, int PV>
 int resident_max_teams_t() {
   int per_cu = 0, dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_resident<NX, NY, TEAM, NT>, NT, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_resident<NX, NY, TEAM, NT, PV>, NT, 0) !=
       hipSuccess)
     return 0;
   int teams = per_cu * ncu / TEAM;
@@ -468,16 +474,17 @@ int resident_max_teams_t() {
 }  // namespace pdk
 
 // Defines resident variant V of the square N x N slice shape: its launcher,
-// its co-resident team capacity, and its team size and block size.
-#define PD_INSTANTIATE_RESIDENT(N, V, TEAM, NT)                                                          \
+// its co-resident team capacity, its team size, block size and FFT pass plan.
+#define PD_INSTANTIATE_RESIDENT(N, V, TEAM, NT, PV)                                                      \
   namespace pdk {                                                                                        \
   hipError_t launch_resident_##N##_##V(int nteams, const Vol* vols, const Range* ranges, int nranges,    \
                                        Ctl* ctl, unsigned* counters, int* abort_flag, int fenced,        \
                                        unsigned spin_limit, hipStream_t st) {                            \
-    return launch_resident_t<N, N, TEAM, NT>(nteams, vols, ranges, nranges, ctl, counters, abort_flag,   \
-                                             fenced, spin_limit, st);                                     \
+    return launch_resident_t<N, N, TEAM, NT, PV>(nteams, vols, ranges, nranges, ctl, counters,           \
+                                                 abort_flag, fenced, spin_limit, st);                     \
   }                                                                                                      \
-  int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT>(); }                 \
+  int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT, PV>(); }             \
   int resident_team_##N##_##V() { return TEAM; }                                                        \
   int resident_threads_##N##_##V() { return NT; }                                                       \
+  int resident_plan_##N##_##V() { return PV; }                                                          \
   }

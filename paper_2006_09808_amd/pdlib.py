@@ -60,7 +60,7 @@ class PdTuneEntry(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("iters", ctypes.c_int),
                 ("path", ctypes.c_int), ("variant", ctypes.c_int), ("team", ctypes.c_int),
                 ("threads", ctypes.c_int), ("rows", ctypes.c_int), ("cols", ctypes.c_int),
-                ("ms", ctypes.c_double)]
+                ("plan", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
 class PdResult(ctypes.Structure):
@@ -104,9 +104,9 @@ def load_library(path=None):
     lib.pd_recovery_stats.argtypes = [c.c_void_p, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
     lib.pd_tune.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.POINTER(PdTuneEntry), c.c_int,
                             c.POINTER(c.c_int)]
-    lib.pd_tune_set.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int]
+    lib.pd_tune_set.argtypes = [c.c_void_p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int]
     lib.pd_tune_get.argtypes = [c.c_void_p, c.c_int, c.c_int, c.POINTER(c.c_int), c.POINTER(c.c_int),
-                                c.POINTER(c.c_int)]
+                                c.POINTER(c.c_int), c.POINTER(c.c_int), c.POINTER(c.c_int)]
     for name in ("pd_create", "pd_solve_batch", "pd_poll", "pd_destroy", "pd_validate",
                  "pd_kernel_norm", "pd_apply_kernel", "pd_kernel_time", "pd_kernel_time_reset",
                  "pd_graph_stats", "pd_arena_usage", "pd_tune", "pd_tune_set", "pd_tune_get",
@@ -319,28 +319,32 @@ class Solver:
 
     def tune(self, nx, ny, nz, iters=20):
         """Time every kernel configuration of the nx x ny shape and make the
-        fastest the context's choice.  Returns the list of timings."""
-        buf = (PdTuneEntry * 32)()
+        fastest the context's choice.  Returns the list of timings: path
+        "resident" (variant, team, threads), "column" (cols, plan of the ny
+        transforms) or "row" (rows, plan of the nx transforms)."""
+        buf = (PdTuneEntry * 64)()
         n = ctypes.c_int(0)
-        st = self.lib.pd_tune(self._ctx, int(nx), int(ny), int(nz), int(iters), buf, 32, ctypes.byref(n))
+        st = self.lib.pd_tune(self._ctx, int(nx), int(ny), int(nz), int(iters), buf, 64, ctypes.byref(n))
         if st != PD_OK:
             raise PdError(st, "pd_tune")
         out = []
         for e in buf[:n.value]:
-            out.append({"path": "resident" if e.path == 0 else "two_launch", "variant": e.variant,
-                        "team": e.team, "threads": e.threads, "rows": e.rows, "cols": e.cols,
+            out.append({"path": ("resident", "column", "row")[e.path], "variant": e.variant,
+                        "team": e.team, "threads": e.threads, "rows": e.rows, "cols": e.cols, "plan": e.plan,
                         "ms": e.ms, "nz": e.nz, "iters": e.iters})
         return out
 
     def tune_get(self, nx, ny):
-        v, r, cl = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
-        st = self.lib.pd_tune_get(self._ctx, int(nx), int(ny), ctypes.byref(v), ctypes.byref(r), ctypes.byref(cl))
+        v, r, cl, px, py = (ctypes.c_int(0) for _ in range(5))
+        st = self.lib.pd_tune_get(self._ctx, int(nx), int(ny), ctypes.byref(v), ctypes.byref(r), ctypes.byref(cl),
+                                  ctypes.byref(px), ctypes.byref(py))
         if st != PD_OK:
             raise PdError(st, "pd_tune_get")
-        return {"variant": v.value, "rows": r.value, "cols": cl.value}
+        return {"variant": v.value, "rows": r.value, "cols": cl.value, "plan_x": px.value, "plan_y": py.value}
 
-    def tune_set(self, nx, ny, variant=-1, rows=0, cols=0):
-        st = self.lib.pd_tune_set(self._ctx, int(nx), int(ny), int(variant), int(rows), int(cols))
+    def tune_set(self, nx, ny, variant=-1, rows=0, cols=0, plan_x=0, plan_y=0):
+        st = self.lib.pd_tune_set(self._ctx, int(nx), int(ny), int(variant), int(rows), int(cols), int(plan_x),
+                                  int(plan_y))
         if st != PD_OK:
             raise PdError(st, "pd_tune_set")
 
@@ -356,7 +360,7 @@ class Solver:
             d = json.load(f)
         for k, v in d.items():
             nx, ny = (int(t) for t in k.split("x"))
-            self.tune_set(nx, ny, v["variant"], v["rows"], v["cols"])
+            self.tune_set(nx, ny, v["variant"], v["rows"], v["cols"], v.get("plan_x", 0), v.get("plan_y", 0))
 
     def graph_stats(self):
         """(steps captured into HIP graphs, steps replayed from one)."""

@@ -200,14 +200,18 @@ void sleep_step() {
 }
 }  // namespace
 
-hipError_t launch_col(int, int, int, int grid, int groups, const Vol* vols, const Range* ranges, int nranges,
-                      Ctl*, int, int, int, hipStream_t) {
+int plan_count(int n) { return (n == 64 || n == 128) ? 2 : 1; }
+
+hipError_t launch_col_p(int n, int, int, int grid, int groups, const Vol* vols, const Range* ranges, int nranges,
+                        Ctl*, int, int precision, int ext, int plan, hipStream_t) {
+  if (plan < 0 || plan >= plan_count(n) || (plan && (precision || ext))) return hipErrorInvalidValue;
   mock::run([=] { check_cover(vols, ranges, nranges, groups, grid, "column launch covers a pair out of range"); });
   return hipSuccess;
 }
 
-hipError_t launch_row(int, int mode, int, int grid, int groups, const Vol* vols, const Range* ranges, int nranges,
-                      Ctl* ctl, int it, int, int, hipStream_t) {
+hipError_t launch_row_p(int n, int mode, int, int grid, int groups, const Vol* vols, const Range* ranges,
+                        int nranges, Ctl* ctl, int it, int precision, int ext, int plan, hipStream_t) {
+  if (plan < 0 || plan >= plan_count(n) || (plan && (precision || ext))) return hipErrorInvalidValue;
   mock::run([=] {
     check_cover(vols, ranges, nranges, groups, grid, "row launch covers a pair out of range");
     if (mode == ROW_ITER) {
@@ -231,6 +235,15 @@ hipError_t launch_row(int, int mode, int, int grid, int groups, const Vol* vols,
     }
   });
   return hipSuccess;
+}
+
+hipError_t launch_col(int n, int mode, int cols, int grid, int groups, const Vol* vols, const Range* ranges,
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+  return launch_col_p(n, mode, cols, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, 0, st);
+}
+hipError_t launch_row(int n, int mode, int rows, int grid, int groups, const Vol* vols, const Range* ranges,
+                      int nranges, Ctl* ctl, int it, int precision, int ext, hipStream_t st) {
+  return launch_row_p(n, mode, rows, grid, groups, vols, ranges, nranges, ctl, it, precision, ext, 0, st);
 }
 
 hipError_t launch_reduce(int nslots, const Vol* vols, const int* slots, Ctl* ctl, int it, int, hipStream_t) {
@@ -295,7 +308,7 @@ hipError_t mock_resident(int nteams, const Vol* vols, const Range* ranges, int n
     if (*abort_flag) return;   // an earlier launch of the round gave up
     check_cover(vols, ranges, nranges, kTeam, nteams * kTeam, "resident launch covers a pair out of range");
     int forced = mock::force_aborts.load();
-    bool give_up = spin_limit < 64;
+    bool give_up = spin_limit == 0;
     while (!give_up && forced > 0 && !mock::force_aborts.compare_exchange_weak(forced, forced - 1)) {
     }
     give_up |= forced > 0;
@@ -315,9 +328,10 @@ hipError_t mock_resident(int nteams, const Vol* vols, const Range* ranges, int n
 int mock_max_teams() { return 16; }
 int mock_team() { return kTeam; }
 int mock_threads() { return 256; }
-const ResidentVariant kVariants[] = {{64, mock_resident, mock_max_teams, mock_team, mock_threads},
-                                     {128, mock_resident, mock_max_teams, mock_team, mock_threads},
-                                     {256, mock_resident, mock_max_teams, mock_team, mock_threads}};
+int mock_plan() { return 0; }
+const ResidentVariant kVariants[] = {{64, mock_resident, mock_max_teams, mock_team, mock_threads, mock_plan},
+                                     {128, mock_resident, mock_max_teams, mock_team, mock_threads, mock_plan},
+                                     {256, mock_resident, mock_max_teams, mock_team, mock_threads, mock_plan}};
 }  // namespace
 
 namespace {
@@ -605,9 +619,9 @@ void t_recovery_forced_giveup() {
   pd_tune_entry e[8];
   int n = 0;
   EXPECT(pd_tune(x.c, 64, 64, 4, 5, e, 8, &n) == PD_OK, "tune under give-up");
-  for (int i = 0; i < n; ++i) EXPECT(e[i].path == 1, "tuner kept a resident variant that gave up");
+  for (int i = 0; i < n; ++i) EXPECT(e[i].path != 0, "tuner kept a resident variant that gave up");
   // an explicit resident choice re-enables the shape
-  EXPECT(pd_tune_set(x.c, 128, 128, 0, 0, 0) == PD_OK, "tune_set");
+  EXPECT(pd_tune_set(x.c, 128, 128, 0, 0, 0, 0, 0) == PD_OK, "tune_set");
   Req f = make_req(128, 128, 2, 50);
   auto t3 = submit(x.c, {&f});
   check_done(x.c, t3[0], f, "re-enabled shape gives up again and recovers");
@@ -629,6 +643,28 @@ void t_recovery_midway() {
   EXPECT(ab == 1, "one aborted round, got %lld", (long long)ab);
   mock::force_aborts = 0;
   mock::step_sleep_us = 0;
+}
+
+void t_tuned_plans() {
+  // the tuner times every plan of each kernel; a chosen plan reaches the
+  // launches (the mock rejects plans a length does not have)
+  Ctx x(128 << 20, PD_FLAG_NO_RESIDENT);
+  pd_tune_entry e[32];
+  int n = 0;
+  EXPECT(pd_tune(x.c, 128, 64, 8, 5, e, 32, &n) == PD_OK, "tune");
+  int cols_plans = 0, rows_plans = 0;
+  for (int i = 0; i < n; ++i) {
+    cols_plans += e[i].path == 1 && e[i].plan == 1;
+    rows_plans += e[i].path == 2 && e[i].plan == 1;
+  }
+  EXPECT(cols_plans >= 1 && rows_plans >= 1, "plans timed: %d column, %d row", cols_plans, rows_plans);
+  EXPECT(pd_tune_set(x.c, 128, 64, -1, 8, 8, 1, 1) == PD_OK, "set plans");
+  int v, r, cl, px, py;
+  EXPECT(pd_tune_get(x.c, 128, 64, &v, &r, &cl, &px, &py) == PD_OK && px == 1 && py == 1, "get plans");
+  EXPECT(pd_tune_set(x.c, 96, 64, -1, 8, 8, 1, 0) == PD_ERR_ARG, "96 has one plan in the mock");
+  Req q = make_req(128, 64, 6, 137, 90, 30);
+  auto t = submit(x.c, {&q});
+  check_done(x.c, t[0], q, "solve under tuned plans");
 }
 
 void t_apply_kernel() {
@@ -659,6 +695,7 @@ const Test kTests[] = {{"single", t_single},
                        {"destroy_while_polling", t_destroy_while_polling},
                        {"recovery_forced_giveup", t_recovery_forced_giveup},
                        {"recovery_midway", t_recovery_midway},
+                       {"tuned_plans", t_tuned_plans},
                        {"apply_kernel", t_apply_kernel}};
 
 }  // namespace

@@ -125,8 +125,8 @@ def test_resident_barrier_giveup_recovers(torch_mod):
     run's iterates up to rounding, a request of another shape in the same
     rounds is unaffected (bitwise), and later requests of the shape keep to
     the two-launch path.  The give-up is forced from the host: the context's
-    test flag lets every barrier poll only twice, so every workgroup still
-    exits through the kernel's own bounded wait."""
+    test flag makes every barrier give up at its first wait, so every
+    workgroup exits through the kernel's own abort path."""
     import paper_2006_09808_amd as pd
     torch = torch_mod
     wa, da = _case(730, 6, 256, 256, 0)
