@@ -283,7 +283,10 @@ double pd_now(void);
  * 4 = TV-model row kernels (inverse row FFT, dual or primal update, forward
  * row FFT; two per iteration), 5 = the 3-D kernel's z transform (forward z
  * FFT, dual prox, inverse z FFT; kind 0 then counts its in-plane column
- * transforms).  pd_kernel_time_reset clears all. */
+ * transforms), 6 = multi-shape resident launches (a whole step of the pairs
+ * of several square shapes in one launch: 64x64, 128x128 and 256x256 volumes
+ * whose chosen resident variant runs the default FFT plan, whenever a step
+ * holds two or more such shapes).  pd_kernel_time_reset clears all. */
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 

@@ -19,6 +19,7 @@
 #include "pd_internal.hpp"
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -519,6 +520,7 @@ struct pd_ctx {
   std::set<std::pair<int, int>> no_resident;
   unsigned spin_limit = kSpinLimit;   // resident barriers' polls before giving up
   void* scratch = nullptr;     // device address of this device's static scratch (pd_apply_kernel_noalloc)
+  int multi_cap = 0;           // workgroups of the multi-shape resident launch one XCD holds at once
   int64_t aborted_rounds = 0, restarted_requests = 0;   // under exec_mu
 
   // captured step graphs of the two-launch path, keyed by launch plan
@@ -534,7 +536,7 @@ struct pd_ctx {
   // kernel timing
   bool time_kernels = false;
   std::mutex tmu;
-  static constexpr int kKinds = 6;        // column, row, resident, TV column, TV row, 3-D z transform
+  static constexpr int kKinds = 7;        // column, row, resident, TV column, TV row, 3-D z transform, multi-shape resident
   int64_t t_launches[kKinds] = {};
   double t_ms[kKinds] = {};
   double t_points[kKinds] = {};           // iterations x slice-pair points processed
@@ -960,6 +962,9 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     int pz, ez, zg, z_off, nzr;              // z: transform length, variant, groups per volume, ranges
     int team;
     const ResidentVariant* rv;
+    bool multi;                              // multi-shape resident launch (team table at range_off)
+    int quota, nteams;                       // multi: workgroups per XCD, teams
+    double multi_pts;                        // multi: slice-pair points of all its teams
     int range_off, nranges, npairs;          // resident: one range table
     int row_off, col_off;                    // two-launch path: row and column tables
   };
@@ -971,15 +976,50 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     return true;
   };
   bool fits = true;
+  // The shape's chosen resident variant, or null for the two-launch path.
+  auto chosen_rv = [&](const GroupKey& gk) -> const ResidentVariant* {
+    const int nx = gk.nx, ny = gk.ny;
+    const pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
+    return (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only &&
+            gk.model != PD_MODEL_TV && gk.nz3 == 0 && !c->no_resident.count({nx, ny}))
+               ? resident_variant(nx, tn.res_variant)
+               : nullptr;
+  };
+  // Several resident shapes whose chosen variants' (shape, FFT plan) is a
+  // body of the multi-shape launch share it (a body gives the same bits as
+  // every variant of its plan), if their teams fit the range table.
+  std::vector<Job*> multi_jobs;
+  std::vector<int> multi_plan;   // FFT plan of each multi job's chosen variant
+  const int multi_cap = c->multi_cap;
+  {
+    int shapes = 0;
+    size_t entries = 0;
+    for (auto& g : groups) {
+      const ResidentVariant* rv = chosen_rv(g.first);
+      if (!rv || multi_body(g.first.nx, rv->plan()) < 0 || multi_cap < multi_team(g.first.nx, rv->plan())) continue;
+      ++shapes;
+      for (Job* j : g.second) entries += (size_t)j->L.P;
+    }
+    // range entries: each team one, each launch (at most one per team)
+    // kXcds + 1 headers, every other job at most four
+    if (shapes >= 2 && entries * (kXcds + 2) + 4 * act.size() + 16 <= c->range_cap)
+      for (auto& g : groups) {
+        const ResidentVariant* rv = chosen_rv(g.first);
+        if (!rv || multi_body(g.first.nx, rv->plan()) < 0 || multi_cap < multi_team(g.first.nx, rv->plan())) continue;
+        for (Job* j : g.second) {
+          multi_jobs.push_back(j);
+          multi_plan.push_back(rv->plan());
+        }
+      }
+  }
   for (auto& g : groups) {
     int nx = g.first.nx, ny = g.first.ny;
     const pd_ctx::Tuned tn = c->tuned.count({nx, ny}) ? c->tuned[{nx, ny}] : pd_ctx::Tuned{};
     const bool tv = g.first.model == PD_MODEL_TV;
     const bool z3 = g.first.nz3 > 0;
-    const ResidentVariant* rv =
-        (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && nx == ny && !any_check_only && !tv &&
-         !z3 && !c->no_resident.count({nx, ny}))
-            ? resident_variant(nx, tn.res_variant) : nullptr;
+    if (!multi_jobs.empty() && std::find(multi_jobs.begin(), multi_jobs.end(), g.second.front()) != multi_jobs.end())
+      continue;   // in the multi-shape launches below
+    const ResidentVariant* rv = chosen_rv(g.first);
     int maxt = rv ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
     if (rv) {
       // the chosen variant was timed at some slice count; when this step's
@@ -1081,10 +1121,81 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       launches.push_back(L);
     }
   }
+  if (!multi_jobs.empty()) {
+    // Multi-shape launches: every pair of the jobs is one team of its shape's
+    // body; teams go to the least loaded XCD of the current launch (largest
+    // teams first), and a team that no XCD of it can take opens the next
+    // launch.  Each XCD's teams then get consecutive ticket ranges.
+    struct TeamRec {
+      int slot, pair, body, size, xcd;
+    };
+    std::vector<TeamRec> recs;
+    for (size_t ji = 0; ji < multi_jobs.size(); ++ji) {
+      Job* j = multi_jobs[ji];
+      const int sz = multi_team(j->req.nx, multi_plan[ji]);
+      const int body = multi_body(j->req.nx, multi_plan[ji]);
+      for (int p = 0; p < j->L.P; ++p) recs.push_back(TeamRec{j->slot, p, body, sz, -1});
+      j->in_resident = true;
+      Vol& V = c->h_vols[j->slot];
+      V.row_groups = V.col_groups = sz;
+    }
+    std::stable_sort(recs.begin(), recs.end(), [](const TeamRec& a, const TeamRec& b) { return a.size > b.size; });
+    std::vector<std::vector<TeamRec>> per_launch(1);
+    std::vector<std::array<int, kXcds>> load(1);
+    load[0].fill(0);
+    for (TeamRec t : recs) {
+      auto& ld = load.back();
+      int x = (int)(std::min_element(ld.begin(), ld.end()) - ld.begin());
+      if (ld[x] + t.size > multi_cap) {
+        per_launch.emplace_back();
+        load.emplace_back();
+        load.back().fill(0);
+        x = 0;
+      }
+      t.xcd = x;
+      load.back()[x] += t.size;
+      per_launch.back().push_back(t);
+    }
+    for (size_t li = 0; li < per_launch.size(); ++li) {
+      auto& ts = per_launch[li];
+      std::stable_sort(ts.begin(), ts.end(), [](const TeamRec& a, const TeamRec& b) { return a.xcd < b.xcd; });
+      Launch L{};
+      L.nx = L.ny = 0;
+      L.resident = true;
+      L.multi = true;
+      L.range_off = (int)k;
+      L.nteams = (int)ts.size();
+      L.quota = *std::max_element(load[li].begin(), load[li].end());
+      // header: index of each XCD's first team, then the team count
+      if (k + kXcds + 1 + ts.size() >= c->range_cap) {
+        fits = false;
+        break;
+      }
+      int ti = 0;
+      for (int x = 0; x <= kXcds; ++x) {
+        while (ti < (int)ts.size() && ts[ti].xcd < x) ++ti;
+        s_ranges[k++] = Range{-1, ti, 0, 0};
+      }
+      int ticket = 0, prev = -1;
+      double pts = 0.0;
+      for (auto& t : ts) {
+        if (t.xcd != prev) {
+          ticket = 0;
+          prev = t.xcd;
+        }
+        s_ranges[k++] = Range{t.slot, ticket, t.pair, t.body};
+        ticket += t.size;
+        pts += (double)c->h_vols[t.slot].nx * c->h_vols[t.slot].ny;
+      }
+      L.npairs = L.nteams;
+      L.multi_pts = pts;
+      launches.push_back(L);
+    }
+  }
   if (!fits) return hipErrorOutOfMemory;   // range table too small: cannot happen with range_cap
   // resident launches report gap partials per team member
   for (auto& L : launches)
-    if (L.resident)
+    if (L.resident && !L.multi)
       for (int i = 0; i < L.nranges; ++i) {
         Vol& V = c->h_vols[s_ranges[L.range_off + i].slot];
         V.row_groups = V.col_groups = L.team;
@@ -1139,6 +1250,19 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
   auto enqueue_resident = [&](bool with_events) -> hipError_t {
     for (auto& L : launches) {
       if (!L.resident) continue;
+      if (L.multi) {
+        // team counters, then the per-XCD tickets and the grid arrival counter
+        const int ticket_base = (L.nteams + kXcds - 1) / kXcds * kXcds;
+        hipError_t r = launch_zero(c->d_counters, align_up(counter_bytes((size_t)ticket_base)), c->stream);
+        if (r != hipSuccess) return r;
+        auto res = [&] {
+          return launch_resident_multi(L.quota, c->d_vols, c->d_ranges + L.range_off, c->d_ctl, c->d_counters,
+                                       c->d_abort, ticket_base, fenced, c->spin_limit, c->stream);
+        };
+        r = with_events ? timed(6, L.multi_pts * K, res) : res();
+        if (r != hipSuccess) return r;
+        continue;
+      }
       // team counters of every team slot of the launch (rounds of 8 teams),
       // then the per-XCD tickets and the grid arrival counter
       const size_t slots_ = (size_t)((L.npairs + kXcds - 1) / kXcds) * kXcds;
@@ -1254,10 +1378,15 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     std::string sig = std::to_string(K) + (any_check ? "c" : "n") + std::to_string(nslot_list) + ":" +
                       std::to_string(c->precision);
     for (auto& L : launches) {
+      if (L.multi) {
+        sig += "|m" + std::to_string(L.quota) + "," + std::to_string(L.nteams) + "," + std::to_string(L.range_off);
+        continue;
+      }
       if (L.resident) {
+        // the variant (its kernel: shape, team, block size and FFT plan) and its arguments
         sig += "|r" + std::to_string(L.nx) + "," + std::to_string(L.rv->team()) + "," +
-               std::to_string(L.rv->threads()) + "," + std::to_string(L.npairs) + "," + std::to_string(L.range_off) +
-               "," + std::to_string(L.nranges);
+               std::to_string(L.rv->threads()) + "," + std::to_string(L.rv->plan()) + "," +
+               std::to_string(L.npairs) + "," + std::to_string(L.range_off) + "," + std::to_string(L.nranges);
         continue;
       }
       sig += "|" + std::string(L.tv ? "tv" : "l1") + (L.z3 ? "z" + std::to_string(L.pz) + "," + std::to_string(L.zg) + "," +
@@ -1743,6 +1872,7 @@ pd_status pd_create(const pd_config* cfg, pd_ctx** out) {
 
   std::unique_ptr<pd_ctx> c(new pd_ctx());
   c->scratch = scratch;
+  c->multi_cap = multi_max_groups_per_xcd();
   c->cfg = *cfg;
   c->device = cfg->device;
   c->precision = cfg->precision;

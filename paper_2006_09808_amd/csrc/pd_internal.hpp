@@ -214,6 +214,18 @@ struct ResidentVariant {
 hipError_t static_scratch(int device, void** ptr);
 std::mutex& static_scratch_lock(int device);
 
+// The multi-shape resident launch (pd_resident_multi.hip): body index and
+// team size of the square n x n shape on FFT plan `plan` in it (-1 / 0: not
+// a body), the
+// co-resident workgroups one XCD holds, and the launch of quota workgroups
+// per XCD over the team table at `table` (kXcds + 1 XCD entries, then the
+// teams; see k_resident_multi).
+int multi_body(int n, int plan);
+int multi_team(int n, int plan);
+int multi_max_groups_per_xcd();
+hipError_t launch_resident_multi(int quota, const Vol* vols, const Range* table, Ctl* ctl, unsigned* counters,
+                                 int* abort_flag, int ticket_base, int fenced, unsigned spin_limit, hipStream_t st);
+
 int resident_variant_count(int n);                      // 0: no resident kernel for n x n
 const ResidentVariant* resident_variant(int n, int v);  // nullptr if out of range
 

@@ -132,39 +132,41 @@ struct Resident {
   static constexpr int NQO = FR::template nq<QO>();
   static constexpr int NQA = FC::template nq<QA>();
   static constexpr int NQB = FC::template nq<QB>();
+  static constexpr int kTeam = TEAM;
+  static constexpr int kThreadsPerGroup = NT;
+  // shared memory of one team member, carved from one byte buffer: the FFT
+  // staging area, F delta of the member's columns ([row][column]), the
+  // twiddles of the row (NX) and column (NY) transforms, the barrier flag
+  static constexpr size_t OFF_DH = (size_t)LDS * sizeof(cpx<float>);
+  static constexpr size_t OFF_TW = OFF_DH + (size_t)CT * NY * sizeof(cpx<float>);
+  static constexpr size_t OFF_FLAG = OFF_TW + (size_t)(NX + NY) * sizeof(cpx<float>);
+  static constexpr size_t SMEM = OFF_FLAG + 16;
+
+  static __device__ __forceinline__ void run(unsigned char* smem, const Vol& V, int pair, int m, unsigned* cnt,
+                                             bool fenced, int* abort_flag, unsigned spin_limit);
 };
 
 // counters: one barrier counter per team slot, then kXcds per-XCD tickets and
 // the grid arrival counter, kCounterStride words apart; zeroed before every
 // launch.
-template <int NX, int NY, int TEAM, int NT, int PV>
-__global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
-                                                 int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
-                                                 int* __restrict__ abort_flag, int nteams, int force_fenced,
-                                                 unsigned spin_limit) {
-  using R = Resident<NX, NY, TEAM, NT, PV>;
-  using FR = typename R::FR;
-  using FC = typename R::FC;
-  using T = float;
-  __shared__ cpx<T> lds[R::LDS];
-  __shared__ cpx<T> dh_s[R::CT * NY];        // F delta of this workgroup's columns, [row][column]
-  __shared__ cpx<T> tw_s[NX + NY];           // twiddles of the row (NX) and column (NY) transforms
-  __shared__ int lds_flag;
-
+//
+// Team formation.  Every workgroup reads the XCD it runs on and takes a
+// ticket among that XCD's workgroups; after one grid-wide arrival all of
+// them know whether each XCD received exactly its quota of `quota`
+// workgroups (the dispatcher deals them out round robin, from whichever XCD
+// is next).  If so, a workgroup is member `ticket - first` of the team of its
+// XCD whose ticket range holds its ticket, and every team lives on one XCD;
+// otherwise the workgroups fall back to XCD b mod 8 and ticket b / 8 (b the
+// workgroup index), with agent-scope fences at every barrier.  Gives the
+// workgroup's XCD (or b mod 8) and ticket, and whether barriers must fence;
+// false if the launch aborted before any state was touched.
+template <int NT>
+__device__ __forceinline__ bool form_team(unsigned* counters, int ticket_base, int quota, int force_fenced,
+                                          int* abort_flag, unsigned spin_limit, int* xcd_out, int* ticket_out,
+                                          bool* fenced_out) {
+  __shared__ int s_xcd, s_ticket, s_fenced;
+  unsigned* tickets = counters + (size_t)ticket_base * kCounterStride;   // per-XCD tickets, grid counter
   const int tid = threadIdx.x;
-  // Team formation.  Every workgroup reads the XCD it runs on and takes a
-  // ticket among that XCD's workgroups; after one grid-wide arrival all of
-  // them know whether each XCD received exactly its quota of TEAM * rounds
-  // workgroups (the dispatcher deals them out round robin, from whichever
-  // XCD is next).  If so, team t = (ticket / TEAM) * 8 + XCD and every team
-  // lives on one XCD; otherwise the workgroups fall back to
-  // t = (b / 8 / TEAM) * 8 + b % 8 with agent-scope fences at every barrier.
-  const int rounds = (int)gridDim.x / (kXcds * TEAM);
-  unsigned* tickets = counters + (size_t)rounds * kXcds * kCounterStride;   // per-XCD tickets, grid counter
-  __shared__ int s_team, s_member, s_fenced;
-  // a launch earlier in the same round gave up: this one does nothing (the
-  // host restarts every request of the round's resident launches)
-  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   if (tid == 0) {
     const unsigned here = __builtin_amdgcn_s_getreg((3 << 11) | 20);   // HW_REG_XCC_ID, bits [3:0]
     unsigned ticket = 0xffffffffu;
@@ -178,33 +180,70 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
       bool balanced = true;
       for (int x = 0; x < kXcds; ++x)
         balanced &= __hip_atomic_load(tickets + x * kCounterStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-                    (unsigned)(TEAM * rounds);
+                    (unsigned)quota;
       const int b = (int)blockIdx.x;
       if (balanced && !force_fenced) {
-        s_team = (int)(ticket / TEAM) * kXcds + (int)here;
-        s_member = (int)(ticket % TEAM);
+        s_xcd = (int)here;
+        s_ticket = (int)ticket;
         fen = 0;
       } else {
-        s_team = ((b / kXcds) / TEAM) * kXcds + b % kXcds;
-        s_member = (b / kXcds) % TEAM;
+        s_xcd = b % kXcds;
+        s_ticket = b / kXcds;
         fen = 1;
       }
     }
     s_fenced = fen;
   }
   __syncthreads();
-  if (s_fenced < 0) return;                   // aborted before any state was touched
-  const int t = s_team;
+  if (s_fenced < 0) return false;
+  *xcd_out = s_xcd;
+  *ticket_out = s_ticket;
+  *fenced_out = s_fenced != 0;
+  return true;
+}
+
+template <int NX, int NY, int TEAM, int NT, int PV>
+__global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
+                                                 int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
+                                                 int* __restrict__ abort_flag, int nteams, int force_fenced,
+                                                 unsigned spin_limit) {
+  using R = Resident<NX, NY, TEAM, NT, PV>;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[R::SMEM];
+  // a launch earlier in the same round gave up: this one does nothing (the
+  // host restarts every request of the round's resident launches)
+  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  // one team size: team t = (ticket / TEAM) * 8 + XCD
+  const int rounds = (int)gridDim.x / (kXcds * TEAM);
+  int xcd, ticket;
+  bool fenced;
+  if (!form_team<NT>(counters, rounds * kXcds, TEAM * rounds, force_fenced, abort_flag, spin_limit, &xcd, &ticket,
+                     &fenced))
+    return;                                   // aborted before any state was touched
+  const int t = (ticket / TEAM) * kXcds + xcd;
   if (t >= nteams) return;                    // padding team of the last XCD round
   int slot, pair, m;
-  find_work_b(ranges, nranges, TEAM, t * TEAM + s_member, slot, pair, m);
+  find_work_b(ranges, nranges, TEAM, t * TEAM + ticket % TEAM, slot, pair, m);
   const Vol& V = vols[slot];
   if (ctl[slot].stop || V.iters <= 0 || V.check_only) return;   // uniform over the team
+  R::run(smem, V, pair, m, counters + (size_t)t * kCounterStride, fenced, abort_flag, spin_limit);
+}
+
+// The K iterations of one team member on slice pair `pair` of volume V:
+// member m of TEAM, barrier counter cnt.
+template <int NX, int NY, int TEAM, int NT, int PV>
+__device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned char* smem, const Vol& V, int pair,
+                                                                    int m, unsigned* cnt, bool fenced,
+                                                                    int* abort_flag, unsigned spin_limit) {
+  using R = Resident<NX, NY, TEAM, NT, PV>;
+  using T = float;
+  cpx<T>* lds = (cpx<T>*)(smem);
+  cpx<T>* dh_s = (cpx<T>*)(smem + OFF_DH);
+  cpx<T>* tw_s = (cpx<T>*)(smem + OFF_TW);
+  int& lds_flag = *(int*)(smem + OFF_FLAG);
+  const int tid = threadIdx.x;
   const int iters = V.iters;
   const bool check = V.check_last != 0;
   const bool final_step = V.final_it == iters - 1;
-  unsigned* cnt = counters + (size_t)t * kCounterStride;
-  const bool fenced = s_fenced != 0;
 
   const size_t plane = (size_t)NX * NY;
   const size_t base = (size_t)pair * plane;
@@ -443,6 +482,69 @@ __global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, c
       int s, n;
       if (FC::template pos<R::QB>(tid, q, r, s, n)) yh_g[(unsigned)(n * NX + c0 + s)] = yh[q][r];
     }
+}
+
+// ---------------------------------------------------------------------------
+// One launch over teams of several slice shapes (uneven volumes iterated
+// together).  Bodies... is a list of Resident<N, N, TEAM, NT, PV> types with
+// one block size NT; a team names the body it runs.  The launch's table (in
+// the range array) starts with kXcds + 1 entries whose `first` is the index
+// of each XCD's first team (the last entry: the team count), followed by
+// the teams as Range{slot, first ticket on its XCD, pair, body}, grouped by
+// XCD in ascending ticket order.  Every XCD receives `quota` workgroups; the
+// host places the teams so that each XCD's teams fit in its quota.
+// ---------------------------------------------------------------------------
+template <typename... Bodies>
+constexpr size_t max_smem() {
+  size_t m = 16;
+  ((m = Bodies::SMEM > m ? Bodies::SMEM : m), ...);
+  return m;
+}
+template <int I, typename B, typename... Rest>
+__device__ __forceinline__ int body_team(int body) {
+  if (body == I) return B::kTeam;
+  if constexpr (sizeof...(Rest) > 0) return body_team<I + 1, Rest...>(body);
+  else return 0;
+}
+template <int I, typename B, typename... Rest>
+__device__ __forceinline__ void body_run(int body, unsigned char* smem, const Vol& V, int pair, int m, unsigned* cnt,
+                                         bool fenced, int* abort_flag, unsigned spin_limit) {
+  if (body == I) {
+    B::run(smem, V, pair, m, cnt, fenced, abort_flag, spin_limit);
+    return;
+  }
+  if constexpr (sizeof...(Rest) > 0) body_run<I + 1, Rest...>(body, smem, V, pair, m, cnt, fenced, abort_flag, spin_limit);
+}
+
+// Two waves per SIMD, as every body reaches alone: the register budget is
+// that of the largest body, not of their union.
+template <int NT, typename... Bodies>
+__global__ __launch_bounds__(NT, 2) void k_resident_multi(const Vol* __restrict__ vols, const Range* __restrict__ table,
+                                                       Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
+                                                       int* __restrict__ abort_flag, int ticket_base, int quota,
+                                                       int force_fenced, unsigned spin_limit) {
+  static_assert(((Bodies::kThreadsPerGroup == NT) && ...), "one block size per launch");
+  __shared__ __attribute__((aligned(16))) unsigned char smem[max_smem<Bodies...>()];
+  if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  int xcd, ticket;
+  bool fenced;
+  if (!form_team<NT>(counters, ticket_base, quota, force_fenced, abort_flag, spin_limit, &xcd, &ticket, &fenced))
+    return;
+  const Range* teams = table + kXcds + 1;
+  int lo = table[xcd].first, hi = table[xcd + 1].first - 1;
+  if (lo > hi || teams[lo].first > ticket) return;        // no team holds this ticket: padding
+  while (lo < hi) {                                        // last team of the XCD starting at or before the ticket
+    const int mid = (lo + hi + 1) >> 1;
+    if (teams[mid].first <= ticket) lo = mid;
+    else hi = mid - 1;
+  }
+  const Range& T = teams[lo];
+  const int m = ticket - T.first;
+  if (m >= body_team<0, Bodies...>(T.pad)) return;        // padding after the XCD's last team
+  const Vol& V = vols[T.slot];
+  if (ctl[T.slot].stop || V.iters <= 0 || V.check_only) return;   // uniform over the team
+  body_run<0, Bodies...>(T.pad, smem, V, T.pair0, m, counters + (size_t)lo * kCounterStride, fenced, abort_flag,
+                         spin_limit);
 }
 
 // Launch of `nteams` teams, rounded up to whole rounds of one team per XCD

@@ -59,7 +59,7 @@ thread_local std::vector<std::function<void()>>* capture = nullptr;
 std::atomic<int> violations{0};
 std::atomic<int> step_sleep_us{0};     // each iteration launch sleeps this long (a slow GPU)
 std::atomic<int> force_aborts{0};      // resident launches to fail, whatever the spin limit
-std::atomic<long> resident_launches{0}, row_launches{0};
+std::atomic<long> resident_launches{0}, row_launches{0}, multi_launches{0};
 std::atomic<int*> abort_word{nullptr};  // the context's abort word, as the resident launches see it
 std::mutex log_mu;
 
@@ -325,6 +325,40 @@ hipError_t mock_resident(int nteams, const Vol* vols, const Range* ranges, int n
   });
   return hipSuccess;
 }
+hipError_t mock_resident_multi(int quota, const Vol* vols, const Range* table, Ctl* ctl, unsigned*, int* abort_flag,
+                               int ticket_base, int, unsigned spin_limit, hipStream_t) {
+  mock::run([=] {
+    mock::resident_launches++;
+    mock::multi_launches++;
+    mock::abort_word = abort_flag;
+    if (*abort_flag) return;
+    const int nteams = table[kXcds].first;
+    if (ticket_base < nteams) mock::violation("multi launch: ticket base below the team count", ticket_base, nteams);
+    const Range* teams = table + kXcds + 1;
+    for (int x = 0; x < kXcds; ++x) {   // each XCD's teams: consecutive tickets within the quota
+      int ticket = 0;
+      for (int t = table[x].first; t < table[x + 1].first; ++t) {
+        if (teams[t].first != ticket) mock::violation("multi launch: team ticket", teams[t].first, ticket);
+        ticket += kTeam;
+      }
+      if (ticket > quota) mock::violation("multi launch: XCD over its quota", ticket, quota);
+    }
+    int forced = mock::force_aborts.load();
+    bool give_up = spin_limit == 0;
+    while (!give_up && forced > 0 && !mock::force_aborts.compare_exchange_weak(forced, forced - 1)) {
+    }
+    give_up |= forced > 0;
+    sleep_step();
+    for (int t = 0; t < nteams; ++t) {
+      const Vol& V = vols[teams[t].slot];
+      if (teams[t].pair0 < 0 || teams[t].pair0 >= V.P) mock::violation("multi launch: pair", teams[t].pair0, V.P);
+      if (ctl[teams[t].slot].stop || V.iters <= 0 || V.check_only) continue;
+      add_count(V, teams[t].pair0, give_up ? (t % 2 ? 1000.0 : 0.5) : (double)V.iters);
+    }
+    if (give_up) *abort_flag = 1;
+  });
+  return hipSuccess;
+}
 int mock_max_teams() { return 16; }
 int mock_team() { return kTeam; }
 int mock_threads() { return 256; }
@@ -343,6 +377,14 @@ hipError_t static_scratch(int, void** ptr) {
   return hipSuccess;
 }
 std::mutex& static_scratch_lock(int) { return g_scratch_mu; }
+
+int multi_body(int n, int plan) { return plan != 0 ? -1 : n == 64 ? 0 : n == 128 ? 1 : n == 256 ? 2 : -1; }
+int multi_team(int n, int plan) { return multi_body(n, plan) >= 0 ? kTeam : 0; }
+int multi_max_groups_per_xcd() { return 8; }
+hipError_t launch_resident_multi(int quota, const Vol* vols, const Range* table, Ctl* ctl, unsigned* counters,
+                                 int* abort_flag, int ticket_base, int fenced, unsigned spin_limit, hipStream_t st) {
+  return mock_resident_multi(quota, vols, table, ctl, counters, abort_flag, ticket_base, fenced, spin_limit, st);
+}
 
 int resident_variant_count(int n) {
   int k = 0;
@@ -667,6 +709,23 @@ void t_tuned_plans() {
   check_done(x.c, t[0], q, "solve under tuned plans");
 }
 
+void t_multi_shape() {
+  // resident shapes of one step share multi-shape launches (8 workgroups per
+  // XCD in the mock: 16 teams of 4 per launch, so 30 pairs need two)
+  Ctx x(512 << 20);
+  long before = mock::multi_launches.load();
+  Req a = make_req(64, 64, 7, 240, 150, 30);
+  Req b = make_req(128, 128, 20, 300);
+  Req c = make_req(256, 256, 33, 170, 0, 10);
+  Req d = make_req(96, 64, 5, 260);
+  auto t = submit(x.c, {&a, &b, &c, &d});
+  check_done(x.c, t[0], a, "64x64x7 in a multi-shape launch");
+  check_done(x.c, t[1], b, "128x128x20 in a multi-shape launch");
+  check_done(x.c, t[2], c, "256x256x33 in a multi-shape launch");
+  check_done(x.c, t[3], d, "96x64x5 beside them");
+  EXPECT(mock::multi_launches.load() > before, "no multi-shape launch ran");
+}
+
 void t_apply_kernel() {
   Ctx x(64 << 20);
   Req q = make_req(48, 32, 5, 0);
@@ -696,6 +755,7 @@ const Test kTests[] = {{"single", t_single},
                        {"recovery_forced_giveup", t_recovery_forced_giveup},
                        {"recovery_midway", t_recovery_midway},
                        {"tuned_plans", t_tuned_plans},
+                       {"multi_shape", t_multi_shape},
                        {"apply_kernel", t_apply_kernel}};
 
 }  // namespace

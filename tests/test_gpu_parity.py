@@ -470,3 +470,37 @@ def test_autotune_configurations_agree(torch_mod, n, nz):
             s.tune_set(nx, ny, -1, 7, 0)
         with pytest.raises(pd.PdError):
             s.tune_set(nx, ny, -1, 0, 0, 5, 0)
+
+
+@pytest.mark.parametrize("v128", [0, 4])
+def test_uneven_shapes_share_one_launch_and_equal_solo(torch_mod, v128):
+    """Volumes of 64x64, 128x128 and 256x256 submitted together run as teams
+    of one multi-shape resident launch per step (each XCD's workgroups hold
+    teams of several shapes); each volume equals its solo run (its own
+    single-shape launches) bitwise, and the oracle on sampled slices.  The
+    128x128 volume runs the default FFT plan (variant 0) or 8 x 4 x 4
+    (variant 4): the launch picks the body of the chosen variant's plan."""
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    cases = [make_case(1201, 5, 64, 64, lam=1e-3, max_iter=70, gap_tol=1e-12, check_every=35),
+             make_case(1202, 6, 128, 128, lam=1e-3, max_iter=60),
+             make_case(1203, 7, 256, 256, lam=1e-3, max_iter=50)]
+    with pd.Solver(arena_bytes=1 << 30, device=0, time_kernels=True) as s:
+        s.tune_set(128, 128, v128)
+        solo = [gpu_solve(s, torch, d, **w.solver_params()) for w, d in cases]
+        s.kernel_time_reset()
+        ins = [torch.from_numpy(d).to("cuda:0") for _, d in cases]
+        outs = [torch.empty_like(x) for x in ins]
+        ts = s.submit([(x, o, w.solver_params()) for x, o, (w, _) in zip(ins, outs, cases)])
+        infos = [s.poll(t, -1) for t in ts]
+        n_multi, ms, _ = s.kernel_time(pd.KIND_MULTI)
+        n_single, _, _ = s.kernel_time(pd.KIND_RESIDENT)
+    _say("multi-shape launches %d (%.2f ms), single-shape resident launches %d" % (n_multi, ms, n_single))
+    assert n_multi >= 1
+    for (w, d), o, info, (chi_solo, info_solo) in zip(cases, outs, infos, solo):
+        assert info["status"] == pd.PD_OK and info["iterations"] == info_solo["iterations"]
+        got = o.cpu().numpy().astype(np.float64)
+        np.testing.assert_array_equal(got, chi_solo)
+        assert info["primal"] == info_solo["primal"]
+        ref, _ = oracle.solve(d[:2].astype(np.float64), **w.solver_params())
+        _parity.check(got[:2], ref, "%dx%d slices 0-1" % (d.shape[1], d.shape[2]))
