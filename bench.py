@@ -141,8 +141,9 @@ def serving(rate, seconds, arena_gb):
     """Open-loop Poisson arrivals: in-plane size uniform over 128^2, 192^2,
     256^2, 384^2, 16-64 slices, gap tolerance 1e-5 (FP64 gap every 10
     iterations), cap 1000 iterations, admission under an arena of arena_gb.
-    Each request is a window of slices of a seeded phantom volume of its
-    size, field maps made on the GPU with the library's forward operator."""
+    Every request is its own seeded phantom (pd_inputs.serving_request_device:
+    the batched workload's recipe, drawn on the GPU), its field map made with
+    the library's forward operator plus 1% noise, all before the run starts."""
     import torch
     import pd_inputs
     import paper_2006_09808_amd as pd
@@ -153,23 +154,19 @@ def serving(rate, seconds, arena_gb):
     with pd.Solver(arena_bytes=int(arena_gb * (1 << 30)), device=0) as s:
         for n in pd_inputs.SERVING_SIZES:
             s.tune(n, n, 40, iters=20)
-        base = {}
-        for i, n in enumerate(pd_inputs.SERVING_SIZES):
-            w = pd_inputs.serving_request(5000 + 100 * i, n, 64)
-            chi_t = torch.from_numpy(w.chi_true.astype(np.float32)).to(dev)
-            field = s.apply_kernel(chi_t).cpu().numpy().astype(np.float64)
-            base[n] = torch.from_numpy(pd_inputs.make_delta(field, w.eta, w.rho).astype(np.float32)).to(dev)
         params = dict(lam=1e-3, tau=1.4, sigma=1.4, theta=1.0, max_iter=1000, gap_tol=1e-5, check_every=10)
         reqs = []
         for (t, n, nz, seed) in sched:
-            off = seed % (64 - nz + 1)
-            d = base[n][off:off + nz]
+            chi_t, eta = pd_inputs.serving_request_device(seed, n, nz, dev)
+            field = s.apply_kernel(chi_t)
+            d = field + 0.01 * field.abs().max() * eta
+            del chi_t, eta, field
             reqs.append(serve.Request(t, d, torch.empty_like(d), params))
         torch.cuda.synchronize()
         summary = serve.run_open_loop(s, reqs)
     summary.update({"arrival_rate_per_s": rate, "duration_s": seconds, "arena_GB": arena_gb,
                     "sizes": list(pd_inputs.SERVING_SIZES), "slices": [16, 64],
-                    "gap_tol": 1e-5, "max_iter": 1000})
+                    "gap_tol": 1e-5, "max_iter": 1000, "inputs": "one seeded phantom per request"})
     return summary
 
 

@@ -275,3 +275,71 @@ def tv_stack(seed, nz, ny, nx, rho=0.01, **params):
     eta = rng.standard_normal(chi.shape)
     w, m = weight_and_mask(chi)
     return TvWorkload(chi, eta, rho, w, m, name="tv_%dx%dx%d" % (nx, ny, nz), **params)
+
+
+# ---------------------------------------------------------------------------
+# Serving requests drawn on the GPU: the same recipe as device_stack (tissue
+# noise, 2-6 needle discs and 0-3 seed ellipses per slice, later objects
+# over earlier ones), each request from its own seed, with the two noise
+# fields drawn on the device so that a thousand independent requests can be
+# made in seconds.  The object geometry is drawn on the host and painted
+# into the device array in drawing order.
+# ---------------------------------------------------------------------------
+
+def device_objects(rng, nz, ny, nx):
+    """(z, y, x, value) of every voxel the discs and ellipses of an nz-slice
+    stack cover, in drawing order (a voxel listed twice takes its last
+    value), as four numpy arrays."""
+    zs, ys, xs, vs = [], [], [], []
+
+    def paint(z, cy, cx, ry, rx, value, ellipse):
+        y0, y1 = max(0, int(cy - ry) - 1), min(ny, int(cy + ry) + 2)
+        x0, x1 = max(0, int(cx - rx) - 1), min(nx, int(cx + rx) + 2)
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        if ellipse:
+            m = ((xx - cx) / rx) ** 2 + ((yy - cy) / ry) ** 2 <= 1.0
+        else:
+            m = (yy - cy) ** 2 + (xx - cx) ** 2 <= ry * ry
+        k = int(m.sum())
+        zs.append(np.full(k, z))
+        ys.append(yy[m])
+        xs.append(xx[m])
+        vs.append(np.full(k, value))
+
+    for z in range(nz):
+        for _ in range(int(rng.integers(2, 7))):
+            r = int(rng.integers(2, 6))
+            r = max(1, min(r, (min(ny, nx) - 1) // 2))
+            v = float(rng.uniform(150.0, 200.0))
+            cy = int(rng.integers(r, ny - r))
+            cx = int(rng.integers(r, nx - r))
+            paint(z, cy, cx, r, r, v, False)
+        for _ in range(int(rng.integers(0, 4))):
+            a, b = (2.5, 1.5) if rng.integers(0, 2) == 0 else (1.5, 2.5)
+            cy = int(rng.integers(min(3, ny // 2), max(ny - 3, ny // 2 + 1)))
+            cx = int(rng.integers(min(3, nx // 2), max(nx - 3, nx // 2 + 1)))
+            paint(z, cy, cx, b, a, 100.0, True)
+    cat = lambda a: np.concatenate(a) if a else np.zeros(0)
+    return cat(zs).astype(np.int64), cat(ys).astype(np.int64), cat(xs).astype(np.int64), cat(vs)
+
+
+def serving_request_device(request_seed, n, nz, device):
+    """One served request's ground truth chi (float32, on `device`) and a
+    standard-normal noise field eta of the same shape, both from its own
+    seed: tissue noise and eta drawn by a device generator seeded with it,
+    the devices painted over the tissue in drawing order."""
+    import torch
+    rng = np.random.default_rng(request_seed)
+    z, y, x, v = device_objects(rng, nz, n, n)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(request_seed))
+    chi = torch.randn((nz, n, n), generator=g, device=device, dtype=torch.float32) * TISSUE_SD
+    eta = torch.randn((nz, n, n), generator=g, device=device, dtype=torch.float32)
+    if v.size:
+        # the last write to a voxel wins: keep each voxel's last object only
+        flat = (z * n + y) * n + x
+        _, last = np.unique(flat[::-1], return_index=True)
+        keep = flat.size - 1 - last
+        idx = torch.from_numpy(flat[keep]).to(device)
+        chi.view(-1)[idx] = torch.from_numpy(v[keep].astype(np.float32)).to(device)
+    return chi, eta

@@ -128,3 +128,56 @@ def test_serving_mix_sampled_against_oracle_and_under_a_small_arena(torch_mod):
         got = r.chi[0:1].cpu().numpy().astype(np.float64)
         _parity.check(got, ref, "request %dx%dx%d, %d iterations, slice 0" % (
             r.delta.shape[2], r.delta.shape[1], r.delta.shape[0], r.result["iterations"]))
+
+
+def test_gap_tolerance_stops_under_poisson_load(torch_mod):
+    """Requests retire on their gap tolerance while others arrive and run:
+    a Poisson mix (300 requests/s) in which every third request uses the
+    identity kernel (its iterates reach a 1e-5 relative gap within a few
+    dozen iterations, so it stops on the gap) and the rest run the dipole
+    kernel to their cap.  Each gap-stopped request stops at a check within
+    one period of where the oracle stops and matches the oracle's iterate at
+    its own count; the capped ones run exactly to the cap."""
+    import paper_2006_09808_amd as pd
+    from paper_2006_09808_amd import serve
+    torch = torch_mod
+    rng = np.random.default_rng(77)
+    t = 0.0
+    reqs, refs = [], []
+    for i in range(24):
+        t += float(rng.exponential(1.0 / 300.0))
+        n = (64, 128, 96)[i % 3]
+        nz = int(rng.integers(2, 9))
+        if i % 3 == 0:
+            delta = rng.normal(size=(nz, n, n)).astype(np.float32)
+            sp = dict(lam=0.2, tau=0.9, sigma=0.9, theta=1.0, max_iter=400, gap_tol=1e-5, check_every=5,
+                      kernel="identity")
+        else:
+            w, delta = make(900 + i, nz, n, n, lam=1e-3, max_iter=60 + 10 * (i % 4))
+            sp = dict(w.solver_params(), gap_tol=1e-5, check_every=10)
+        d = torch.from_numpy(delta).to("cuda:0")
+        reqs.append(serve.Request(t, d, torch.empty_like(d), sp))
+        refs.append(delta)
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        summary = serve.run_open_loop(s, reqs)
+    _say("mix of %d requests: p50 %.1f ms p99 %.1f ms, cap hits %.2f" % (
+        summary["requests"], summary["p50_s"] * 1e3, summary["p99_s"] * 1e3, summary["cap_hit_fraction"]))
+    assert summary["ok"] == len(reqs)
+    stopped = 0
+    for r, delta in zip(reqs, refs):
+        res = r.result
+        sp = r.params
+        got = r.chi.cpu().numpy().astype(np.float64)
+        if sp.get("kernel") == "identity":
+            base = {k: v for k, v in sp.items() if k != "kernel"}
+            _, iref = oracle.solve(delta.astype(np.float64), kind="identity", **base)
+            assert res["iterations"] < sp["max_iter"] and res["iterations"] % sp["check_every"] == 0
+            assert res["rel_gap"] <= sp["gap_tol"]
+            assert abs(res["iterations"] - iref["iterations"]) <= sp["check_every"]
+            ref, _ = oracle.solve(delta.astype(np.float64), kind="identity",
+                                  **dict(base, gap_tol=0.0, max_iter=res["iterations"]))
+            _parity.check(got, ref, "identity %s stopped at %d" % (delta.shape, res["iterations"]))
+            stopped += 1
+        else:
+            assert res["iterations"] == sp["max_iter"]
+    assert stopped == 8

@@ -51,3 +51,22 @@ def test_serving_schedule():
     assert 1000 < len(s) < 1400                        # 20/s for 60 s
     assert {r[1] for r in s} == set(P.SERVING_SIZES)
     assert min(r[2] for r in s) >= 16 and max(r[2] for r in s) <= 64
+
+
+def test_serving_requests_drawn_on_the_gpu_follow_the_stack_recipe():
+    """The per-request geometry of the GPU-drawn serving inputs is the one
+    device_slice draws from the same generator state, slice by slice."""
+    from pd_inputs.phantoms import device_objects, device_slice
+    for seed in range(4):
+        nz, ny, nx = 5, 48, 64
+        z, y, x, v = device_objects(np.random.default_rng(seed), nz, ny, nx)
+        rng = np.random.default_rng(seed)
+        got = np.zeros((nz, ny, nx))
+        cov = np.zeros((nz, ny, nx), dtype=bool)
+        for a, b, c, d in zip(z, y, x, v):
+            got[a, b, c] = d
+            cov[a, b, c] = True
+        for k in range(nz):
+            val, c = device_slice(rng, ny, nx)
+            assert np.array_equal(cov[k], c)
+            assert np.array_equal(got[k][c], val[c])
