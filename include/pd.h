@@ -63,7 +63,7 @@ enum { PD_FP32 = 0, PD_FP64 = 1 };                      /* pd_config.precision *
  *                        kz on the nz grid with slice thickness voxel_z
  *                        (the paper's "all three dimensions"; Sec. II-A).
  *                        It couples the slices: every iteration transforms
- *                        along z too.  L1 model only; nz >= 2 and a
+ *                        along z too.  Both models; nz >= 2 and a
  *                        supported length like nx and ny.                    */
 enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1, PD_KERNEL_DIPOLE_3D = 2 };
 /* pd_request.model:
@@ -80,7 +80,12 @@ enum { PD_KERNEL_DIPOLE = 0, PD_KERNEL_IDENTITY = 1, PD_KERNEL_DIPOLE_3D = 2 };
  *                are real per-voxel arrays; G is the in-plane forward
  *                difference divided by the voxel size, zero at the last column
  *                and row (slices stay independent), with the isotropic
- *                norm |(g_x, g_y)|.  Runs exactly max_iter iterations. */
+ *                norm |(g_x, g_y)|.  With PD_KERNEL_DIPOLE_3D the model is
+ *                taken in three dimensions (Sec. II-A): A is the 3-D kernel
+ *                and G gains the z difference divided by voxel_z, zero at
+ *                the last slice, with the norm |(g_x, g_y, g_z)| and the step
+ *                bound's extra 4/voxel_z^2.  Runs exactly max_iter
+ *                iterations. */
 enum { PD_MODEL_L1 = 0, PD_MODEL_TV = 1 };
 
 /* pd_config.flags */

@@ -494,6 +494,7 @@ struct Blue {
   static __device__ __forceinline__ bool pos(int tid, int q, int r, int& s, int& n) {
     return F0::template pos<Q>(tid, q, r, s, n);
   }
+  static __device__ __forceinline__ int lidx(int s, int n) { return F0::lidx(s, n); }
 
   template <int DIR>
   static __device__ __forceinline__ void run(cpx<T> (&in)[nq<L0>()][L0], cpx<T> (&out)[nq<L0>()][L0], cpx<T>* lds,

@@ -244,21 +244,25 @@ struct Layout {
   int ext_row, ext_col;             // kernel variants of the default tiles
   size_t field;                     // one [P][ny][nx] complex buffer
   size_t off_chi, off_yhat, off_dhat, off_ex, off_ex2, off_prow, off_pcol;
-  // weighted TV model: over-relaxed primal, duals p, q_x, q_y, packed W, M, delta
-  size_t off_chibar, off_p, off_qx, off_qy, off_w, off_m, off_d;
+  // weighted TV model: over-relaxed primal, duals p, q_x, q_y (q_z), packed W, M, delta
+  size_t off_chibar, off_p, off_qx, off_qy, off_qz, off_w, off_m, off_d;
   size_t total;
   bool separate_ex2;
   bool tv;
-  bool unpacked;                    // 3-D kernel: one slice per plane, P = nz
+  bool unpacked;                    // 3-D kernel, L1 model: one slice per plane, P = nz
+  bool tv3;                         // 3-D kernel, TV model: pairs, exchange of nz planes
+  int planes;                       // planes of the exchange buffer (column kernels' "pairs")
   int zgroups, ext_z;               // 3-D kernel: z-transform workgroups, kernel variant
 };
 
 Layout layout_of(const pd_request& r, int precision) {
   Layout L{};
   size_t esz = precision == PD_FP64 ? 16 : 8;
-  L.unpacked = r.kernel == PD_KERNEL_DIPOLE_3D;
+  L.unpacked = r.kernel == PD_KERNEL_DIPOLE_3D && r.model != PD_MODEL_TV;
+  L.tv3 = r.kernel == PD_KERNEL_DIPOLE_3D && r.model == PD_MODEL_TV;
   L.P = L.unpacked ? r.nz : (r.nz + 1) / 2;
-  if (L.unpacked) {
+  L.planes = L.tv3 ? r.nz : L.P;
+  if (r.kernel == PD_KERNEL_DIPOLE_3D) {
     // z transforms: strips of 8 of the nx ny columns of the [nz][ny nx] view
     L.zgroups = ceil_div(r.nx * r.ny, 8);
     L.ext_z = axis_ext(r.nz, r.nx * r.ny, 8);
@@ -279,10 +283,11 @@ Layout layout_of(const pd_request& r, int precision) {
     L.off_p = o; o += L.field;
     L.off_qx = o; o += L.field;
     L.off_qy = o; o += L.field;
+    if (L.tv3) { L.off_qz = o; o += L.field; }
     L.off_w = o; o += L.field;
     L.off_m = o; o += L.field;
     L.off_d = o; o += L.field;
-    L.off_ex = o; o += L.field;
+    L.off_ex = o; o += align_up((size_t)L.planes * r.nx * r.ny * esz);
     L.off_ex2 = L.off_ex;
     L.total = o;
     return L;
@@ -379,7 +384,6 @@ pd_status validate(const pd_request* r, int precision, double* norm_out, bool ch
   if (!axis_ok(r->nx) || !axis_ok(r->ny) || r->nz < 1) return PD_ERR_SIZE;
   pd_status ks = kernel_args(r);
   if (ks != PD_OK) return ks;
-  if (r->kernel == PD_KERNEL_DIPOLE_3D && r->model != PD_MODEL_L1) return PD_ERR_ARG;
   if (!isfin(r->lambda) || r->lambda < 0) return PD_ERR_ARG;
   if (r->max_iter < 0) return PD_ERR_ARG;
   if (!isfin(r->gap_tol) || r->gap_tol < 0) return PD_ERR_ARG;
@@ -728,6 +732,11 @@ void fill_vol(pd_ctx* c, const Job& j, Vol& V) {
     V.pdual = base + j.L.off_p;
     V.qx = base + j.L.off_qx;
     V.qy = base + j.L.off_qy;
+    if (j.L.tv3) {
+      V.qz = base + j.L.off_qz;
+      V.tv3 = 1;
+      V.inv_dz = 1.0 / j.req.voxel_z;
+    }
     V.wgt = base + j.L.off_w;
     V.msk = base + j.L.off_m;
     V.dpk = base + j.L.off_d;
@@ -819,7 +828,7 @@ hipError_t setup_job(pd_ctx* c, Job& j) {
   fill_vol(c, j, V);
   hipError_t e = hipMemcpyAsync(c->d_vols + j.slot, &V, sizeof(Vol), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
-  if (j.L.unpacked) {
+  if (j.L.unpacked || j.L.tv3) {
     Vol& Z = c->h_vols[c->zoff + j.slot];
     fill_zvol(j, V, Z);
     if ((e = hipMemcpyAsync(c->d_vols + c->zoff + j.slot, &Z, sizeof(Vol), hipMemcpyHostToDevice, c->stream)) !=
@@ -967,6 +976,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     double multi_pts;                        // multi: slice-pair points of all its teams
     int range_off, nranges, npairs;          // resident: one range table
     int row_off, col_off;                    // two-launch path: row and column tables
+    int ncolp;                               // two-launch path: planes of the column launches
   };
   std::vector<Launch> launches;
   size_t k = 0;
@@ -1100,10 +1110,11 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       L.nranges = (int)g.second.size();
       L.col_off = (int)k;
       np = 0;
-      for (Job* j : g.second) {
+      for (Job* j : g.second) {   // column launches run over the exchange planes
         fits &= push_range(j->slot, np * L.cg, 0);
-        np += j->L.P;
+        np += j->L.planes;
       }
+      L.ncolp = np;
       if (z3) {   // one z-view range per volume
         Job* j0 = g.second.front();
         L.z3 = true;
@@ -1204,7 +1215,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     Vol& V = c->h_vols[j->slot];
     V.col_parts = j->L.unpacked ? j->L.zgroups : V.P * V.col_groups;
     s_vols[j->slot] = V;
-    if (j->L.unpacked) {
+    if (j->L.unpacked || j->L.tv3) {
       fill_zvol(*j, V, c->h_vols[c->zoff + j->slot]);
       s_vols[c->zoff + j->slot] = c->h_vols[c->zoff + j->slot];
     }
@@ -1290,17 +1301,51 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
           const Range* rcol = c->d_ranges + L.col_off;
           double pts = (double)L.npairs * L.nx * L.ny;
           auto col = [&] {
-            return launch_col_p(L.py, COL_ITER, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+            return launch_col_p(L.py, COL_ITER, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                                 it, c->precision, L.ec, L.plany, c->stream);
           };
           auto row = [&] {
             return launch_row_p(L.px, ROW_ITER, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
                                 it, c->precision, L.er, L.planx, c->stream);
           };
+          if (L.tv && L.z3) {
+            // TV model in three dimensions, per half iteration: F_y per plane,
+            // (F_z, D / (nx ny nz), F_z^-1) on the z view, F_y^-1 per plane,
+            // then the dual or primal row kernel over the pairs
+            const Range* rz = c->d_ranges + L.z_off;
+            auto cfwd = [&] {
+              return launch_col(L.py, COL_FWD, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, c->stream);
+            };
+            auto zk = [&] {
+              return launch_col(L.pz, COL_TV, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
+                                c->precision, L.ez, c->stream);
+            };
+            auto cinv = [&] {
+              return launch_col(L.py, COL_INV, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+                                it, c->precision, L.ec, c->stream);
+            };
+            for (int half = 0; half < 2; ++half) {
+              r = with_events ? timed(3, pts, cfwd) : cfwd();
+              if (r != hipSuccess) return r;
+              r = with_events ? timed(5, pts, zk) : zk();
+              if (r != hipSuccess) return r;
+              r = with_events ? timed(3, pts, cinv) : cinv();
+              if (r != hipSuccess) return r;
+              const int mode = half == 0 ? ROW_TV3_DUAL : ROW_TV3_PRIMAL;
+              auto rk = [&] {
+                return launch_row(L.px, mode, L.rows, L.npairs * L.rg, L.rg, c->d_vols, rrow, L.nranges, c->d_ctl,
+                                  it, c->precision, L.er, c->stream);
+              };
+              r = with_events ? timed(4, pts, rk) : rk();
+              if (r != hipSuccess) return r;
+            }
+            continue;
+          }
           if (L.z3) {   // 3-D kernel: F_y, (F_z, dual prox, F_z^-1) on the z view, F_y^-1, row kernel
             const Range* rz = c->d_ranges + L.z_off;
             auto cfwd = [&] {
-              return launch_col(L.py, COL_FWD, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+              return launch_col(L.py, COL_FWD, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                                 it, c->precision, L.ec, c->stream);
             };
             auto zk = [&] {
@@ -1308,7 +1353,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
                                 c->precision, L.ez, c->stream);
             };
             auto cinv = [&] {
-              return launch_col(L.py, COL_INV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+              return launch_col(L.py, COL_INV, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                                 it, c->precision, L.ec, c->stream);
             };
             r = with_events ? timed(0, pts, cfwd) : cfwd();
@@ -1323,7 +1368,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
           }
           if (L.tv) {
             auto col_tv = [&] {
-              return launch_col(L.py, COL_TV, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+              return launch_col(L.py, COL_TV, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                                 it, c->precision, L.ec, c->stream);
             };
             auto row_tv = [&](int mode) {
@@ -1352,7 +1397,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
           if (L.resident || L.tv) continue;
           const Range* rcol = c->d_ranges + L.col_off;
           if (L.z3) {   // F_y of the check buffer in place, then F_z and the partials on the z view
-            r = launch_col(L.py, COL_FWD_CHK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+            r = launch_col(L.py, COL_FWD_CHK, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                            K - 1, c->precision, L.ec, c->stream);
             if (r != hipSuccess) return r;
             r = launch_col(L.pz, COL_CHECK, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, c->d_ranges + L.z_off,
@@ -1360,7 +1405,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
             if (r != hipSuccess) return r;
             continue;
           }
-          r = launch_col_p(L.py, COL_CHECK, L.cols, L.npairs * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
+          r = launch_col_p(L.py, COL_CHECK, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                            K - 1, c->precision, L.ec, L.plany, c->stream);
           if (r != hipSuccess) return r;
         }
@@ -1395,7 +1440,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
              std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
              std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
              std::to_string(L.row_off) + "," + std::to_string(L.col_off) + "," + std::to_string(L.planx) + "," +
-             std::to_string(L.plany);
+             std::to_string(L.plany) + "," + std::to_string(L.ncolp);
     }
     auto& G = c->graphs[sig];
     G.last_use = ++c->graph_clock;

@@ -33,6 +33,7 @@ struct Vol {
   void* pdual;           // data-term dual p
   void* qx;              // gradient dual, x component
   void* qy;              // gradient dual, y component
+  void* qz;              // gradient dual, z component (model in three dimensions)
   void* wgt;             // weights W
   void* msk;             // mask M
   void* dpk;             // field map delta
@@ -41,6 +42,7 @@ struct Vol {
   double tau, sigma, lam, theta;
   double gap_tol;
   double inv_dx, inv_dy; // 1 / voxel size (TV model's gradient)
+  double inv_dz;         // 1 / slice thickness (TV model in three dimensions), else 0
   double knorm;          // max |D| (TV model's step check)
   double gap_norm;       // 1 / (points of one transform): 1/(nx ny), or 1/(nx ny nz) for the 3-D kernel
   int nx, ny, nz, P;
@@ -56,6 +58,8 @@ struct Vol {
   int model;          // 0: L1 prior on chi, 1: weighted TV (Eq. (1))
   int unpacked;       // 3-D kernel: one slice per complex plane (imaginary part 0), P = nz
   int col_parts;      // column-kernel gap partial entries (P col_groups; the z view's groups in 3-D)
+  int tv3;            // TV model in three dimensions: image-domain fields pair-interleaved
+                      //   [P][ny][nx], the exchange buffer nz unpacked planes [nz][ny][nx]
 };
 
 // Device-side control/result block of one resident request.  16-byte
@@ -139,7 +143,8 @@ __device__ __forceinline__ void find_work(const Range* __restrict__ ranges, int 
 // COL_ITER.  COL_FWD_CHK: forward, in place in the check buffer, on check steps.
 enum ColMode { COL_ITER = 0, COL_CHECK = 1, COL_SETUP = 2, COL_APPLY = 3, COL_TV = 4, COL_FWD = 5, COL_INV = 6,
                COL_FWD_CHK = 7 };
-enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2, ROW_TV_DUAL = 3, ROW_TV_PRIMAL = 4 };
+enum RowMode { ROW_ITER = 0, ROW_FWD_PLANAR = 1, ROW_INV_PLANAR = 2, ROW_TV_DUAL = 3, ROW_TV_PRIMAL = 4,
+               ROW_TV3_DUAL = 5, ROW_TV3_PRIMAL = 6 };
 
 constexpr int kThreads = 256;
 

@@ -496,6 +496,8 @@ hipError_t launch_row_t(int mode, int grid, int groups, const Vol* vols, const R
     case ROW_INV_PLANAR: hipLaunchKernelGGL((k_row<T, N, S, ROW_INV_PLANAR, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case ROW_TV_DUAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_DUAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     case ROW_TV_PRIMAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV_PRIMAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV3_DUAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV3_DUAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
+    case ROW_TV3_PRIMAL: hipLaunchKernelGGL((k_row_tv<T, N, S, ROW_TV3_PRIMAL, EXT>), gr, bl, 0, st, vols, ranges, nranges, ctl, groups, it); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

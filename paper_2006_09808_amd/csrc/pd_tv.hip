@@ -4,7 +4,8 @@
 //
 //     tau sigma ||K||^2 < 1,   ||K||^2 <= max|W|^2 max|D|^2 + max|M|^2 (4/dx^2 + 4/dy^2),
 //
-// which needs the maxima of W and M, known only on the device.
+// (+ 4/dz^2 for the model in three dimensions, with D the 3-D kernel), which
+// needs the maxima of W and M, known only on the device.
 #include "pd_internal.hpp"
 #include "pd_fft.hpp"
 
@@ -64,7 +65,7 @@ __global__ void k_tv_check(const Vol* __restrict__ vols, Ctl* __restrict__ ctl, 
   const double wmax = __longlong_as_double((long long)C.wmax_bits);
   const double mmax = __longlong_as_double((long long)C.mmax_bits);
   const double L2 = wmax * wmax * V.knorm * V.knorm +
-                    mmax * mmax * 4.0 * (V.inv_dx * V.inv_dx + V.inv_dy * V.inv_dy);
+                    mmax * mmax * 4.0 * (V.inv_dx * V.inv_dx + V.inv_dy * V.inv_dy + V.inv_dz * V.inv_dz);
   if (C.bad_input) {
     C.status = 1;
     C.stop = 1;

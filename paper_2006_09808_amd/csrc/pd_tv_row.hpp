@@ -25,6 +25,21 @@
 // delta and every dual are real per slice, so the pair packing z = a + i b
 // carries them unchanged (the projection is taken per slice: .x for slice
 // 2p, .y for slice 2p+1).
+//
+// The model in three dimensions (ROW_TV3_*: D the 3-D dipole kernel, G the
+// 3-D forward difference, the z difference divided by the slice thickness
+// and zero at the last slice): the image-domain fields keep the pair layout,
+// but the 3-D transform needs each slice's row spectrum on its own plane, so
+// the exchange buffer holds nz planes and the column kernels run
+//   F_y per plane, (F_z, D / (nx ny nz), F_z^-1) on the z view, F_y^-1 per plane
+// in place of COL_TV.  The row kernel of pair p reads planes 2p and 2p+1 as
+// Z = X'_2p + i X'_2p+1: both are row spectra of real rows, so one inverse
+// transform returns the pair (slice 2p in the real, 2p+1 in the imaginary
+// part).  After the forward transform of the pair it splits the spectrum by
+// the symmetry of real rows, A(k) = (Z(k) + conj Z(-k)) / 2 and
+// B(k) = (Z(k) - conj Z(-k)) / 2i, through LDS.  The z difference of slice
+// 2p+1 reads the next pair's real part, G*_z of slice 2p the previous pair's
+// imaginary part, both completed by the previous launch.
 #pragma once
 
 #include "pd_fft.hpp"
@@ -40,6 +55,8 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   using F = AxisFft<T, NX, S, kThreads, false, EXT>;
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
+  constexpr bool Z3 = MODE == ROW_TV3_DUAL || MODE == ROW_TV3_PRIMAL;
+  constexpr bool DUAL = MODE == ROW_TV_DUAL || MODE == ROW_TV3_DUAL;
   __shared__ cpx<T> lds[F::LDS_ELEMS];
   __shared__ cpx<T> tw_s[F::TW_MAX];
 
@@ -51,7 +68,8 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   const int ny = V.ny;
   const int len = EXT == 2 ? V.nx : NX;     // true row length (and row stride)
   const int r0 = g * S;
-  const size_t base = (size_t)pair * (size_t)len * ny + (size_t)r0 * len;
+  const size_t plane = (size_t)len * ny;
+  const size_t base = (size_t)pair * plane + (size_t)r0 * len;
   auto inb = [&](int s, int n) -> bool {
     if constexpr (EXT == 0) return true;
     else return r0 + s < ny && n < len;
@@ -60,24 +78,38 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   __syncthreads();
   const cpx<T>* tw = tw_s;
 
+  // 3-D: slices 2p and 2p+1 (the second absent for the last pair of odd nz);
+  // z differences 2p -> 2p+1 and 2p+1 -> 2p+2 exist while both ends do
+  const bool has_b = !Z3 || 2 * pair + 1 < V.nz;
+  const bool za_ok = Z3 && has_b;
+  const bool zb_ok = Z3 && 2 * pair + 2 < V.nz;
   cpx<T> a[F::template nq<QI>()][QI];
   cpx<T> b[F::template nq<QO>()][QO];
-  cpx<T>* __restrict__ ex = gmem((cpx<T>*)V.ex) + base;
+  cpx<T>* __restrict__ ex = gmem((cpx<T>*)V.ex) + (Z3 ? (size_t)(2 * pair) * plane + (size_t)r0 * len : base);
 #pragma unroll
   for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
     for (int r = 0; r < QI; ++r) {
       int s, n;
       if constexpr (EXT != 0) a[q][r] = mk((T)0, (T)0);
-      if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) a[q][r] = ex[(size_t)s * len + n];
+      if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) {
+        const size_t o = (size_t)s * len + n;
+        a[q][r] = ex[o];
+        if constexpr (Z3) {   // Z = X'_2p + i X'_2p+1
+          if (has_b) {
+            const cpx<T> xb = ex[o + plane];
+            a[q][r] = mk(a[q][r].x - xb.y, a[q][r].y + xb.x);
+          }
+        }
+      }
     }
   F::template run<+1>(a, b, lds, tw, tid, len);
 
   const T sig = (T)V.sigma;
-  const T idx = (T)V.inv_dx, idy = (T)V.inv_dy;
+  const T idx = (T)V.inv_dx, idy = (T)V.inv_dy, idz = (T)V.inv_dz;
   const cpx<T>* __restrict__ msk = gmem((const cpx<T>*)V.msk) + base;
   bool store_ex = true;
-  if constexpr (MODE == ROW_TV_DUAL) {
+  if constexpr (DUAL) {
     const T damp = (T)(1.0 / (1.0 + V.sigma / V.lam));
     cpx<T>* __restrict__ pd = gmem((cpx<T>*)V.pdual) + base;
     cpx<T>* __restrict__ qxp = gmem((cpx<T>*)V.qx) + base;
@@ -104,14 +136,28 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
           const T vya = qy0.x + sig * m.x * ((cd.x - c0.x) * idy);
           const T vxb = qx0.y + sig * m.y * ((cr.y - c0.y) * idx);
           const T vyb = qy0.y + sig * m.y * ((cd.y - c0.y) * idy);
-          const T sa = fmax((T)1, sqrt(vxa * vxa + vya * vya));
-          const T sb = fmax((T)1, sqrt(vxb * vxb + vyb * vyb));
-          qxp[o] = mk(vxa / sa, vxb / sb);
-          qyp[o] = mk(vya / sa, vyb / sb);
+          if constexpr (Z3) {
+            cpx<T>* __restrict__ qzp = gmem((cpx<T>*)V.qz) + base;
+            const cpx<T> qz0 = qzp[o];
+            const T gza = za_ok ? (c0.y - c0.x) * idz : (T)0;
+            const T gzb = zb_ok ? (cb[o + (ptrdiff_t)plane].x - c0.y) * idz : (T)0;
+            const T vza = qz0.x + sig * m.x * gza;
+            const T vzb = qz0.y + sig * m.y * gzb;
+            const T sa = fmax((T)1, sqrt(vxa * vxa + vya * vya + vza * vza));
+            const T sb = fmax((T)1, sqrt(vxb * vxb + vyb * vyb + vzb * vzb));
+            qxp[o] = mk(vxa / sa, vxb / sb);
+            qyp[o] = mk(vya / sa, vyb / sb);
+            qzp[o] = mk(vza / sa, vzb / sb);
+          } else {
+            const T sa = fmax((T)1, sqrt(vxa * vxa + vya * vya));
+            const T sb = fmax((T)1, sqrt(vxb * vxb + vyb * vyb));
+            qxp[o] = mk(vxa / sa, vxb / sb);
+            qyp[o] = mk(vya / sa, vyb / sb);
+          }
           b[q][r] = mk(w.x * pn.x, w.y * pn.y);
         }
       }
-  } else {  // ROW_TV_PRIMAL
+  } else {  // ROW_TV_PRIMAL, ROW_TV3_PRIMAL
     const T tau = (T)V.tau, theta = (T)V.theta;
     const bool pad_imag = V.half_last && pair == V.P - 1;
     cpx<T>* __restrict__ chi = gmem((cpx<T>*)V.chi) + base;
@@ -149,6 +195,20 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
             ta += mu.x * qu.x * idy;
             tb += mu.y * qu.y * idy;
           }
+          if constexpr (Z3) {   // differences 2p -> 2p+1, 2p+1 -> 2p+2 and 2p-1 -> 2p
+            const cpx<T>* __restrict__ qzp = gmem((const cpx<T>*)V.qz) + base;
+            const cpx<T> qz0 = qzp[o];
+            if (za_ok) {
+              const T f = m0.x * qz0.x * idz;
+              ta -= f;
+              tb += f;
+            }
+            if (zb_ok) tb -= m0.y * qz0.y * idz;
+            if (pair >= 1) {
+              const cpx<T> mp = msk[o - (ptrdiff_t)plane], qp = qzp[o - (ptrdiff_t)plane];
+              ta += mp.y * qp.y * idz;
+            }
+          }
           const T na = x0.x - tau * u.x - tau * ta;
           const T nb = pad_imag ? (T)0 : x0.y - tau * u.y - tau * tb;
           chi[o] = mk(na, nb);
@@ -162,13 +222,39 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   if (store_ex) {
     F::sync_before_reuse();
     F::template run<-1>(b, a, lds, tw, tid, len);
+    if constexpr (Z3) {
+      // split the pair's row spectrum into the two slices' spectra: Z(-k)
+      // sits in another lane, so the row goes through LDS
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < F::template nq<QI>(); ++q)
+      for (int q = 0; q < F::template nq<QI>(); ++q)
 #pragma unroll
-      for (int r = 0; r < QI; ++r) {
-        int s, n;
-        if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) ex[(size_t)s * len + n] = a[q][r];
-      }
+        for (int r = 0; r < QI; ++r) {
+          int s, n;
+          if (F::template pos<QI>(tid, q, r, s, n)) lds[F::lidx(s, n)] = a[q][r];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QI; ++r) {
+          int s, n;
+          if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) {
+            const cpx<T> z = a[q][r], zm = lds[F::lidx(s, n == 0 ? 0 : len - n)];
+            const size_t o = (size_t)s * len + n;
+            ex[o] = mk((z.x + zm.x) * (T)0.5, (z.y - zm.y) * (T)0.5);
+            if (has_b) ex[o + plane] = mk((z.y + zm.y) * (T)0.5, (zm.x - z.x) * (T)0.5);
+          }
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < F::template nq<QI>(); ++q)
+#pragma unroll
+        for (int r = 0; r < QI; ++r) {
+          int s, n;
+          if (F::template pos<QI>(tid, q, r, s, n) && inb(s, n)) ex[(size_t)s * len + n] = a[q][r];
+        }
+    }
   }
 }
 

@@ -196,10 +196,17 @@ def test_3d_kernel_request_rules():
     assert nb3 > nb2                       # unpacked planes and the 3-D D table
     assert pd.validate(64, 64, 43, **k3) > 0          # Bluestein along z
     for bad, status in ((dict(voxel_z=0.0), pd.PD_ERR_ARG), (dict(voxel_z=float("nan")), pd.PD_ERR_ARG),
-                        (dict(model="tv", weight_ptr=3, mask_ptr=4, lam=10.0), pd.PD_ERR_ARG)):
+                        (dict(model="tv", weight_ptr=3, mask_ptr=4, lam=10.0, voxel_z=-1.0), pd.PD_ERR_ARG)):
         with pytest.raises(pd.PdError) as e:
             pd.validate(64, 64, 8, **dict(k3, **bad))
         assert e.value.status == status
+    # the TV model in three dimensions: pair-layout fields plus q_z, an
+    # exchange of nz planes and the 3-D D table
+    tv = dict(model="tv", weight_ptr=3, mask_ptr=4, lam=10.0)
+    nb_tv2 = pd.validate(64, 64, 8, **tv)
+    nb_tv3 = pd.validate(64, 64, 8, **dict(k3, **tv))
+    field = 4 * 64 * 64 * 8
+    assert nb_tv3 - nb_tv2 >= field + 4 * 64 * 64 * 8 + 7 * 64 * 64 * 4
     for nz in (1, 385):
         with pytest.raises(pd.PdError) as e:
             pd.validate(64, 64, nz, **k3)
