@@ -49,6 +49,9 @@ def parse():
                     help="force this resident-kernel variant instead of the autotuned choice")
     ap.add_argument("--tv-only", action="store_true",
                     help="run only the weighted-TV workload line (for profiling its kernels)")
+    ap.add_argument("--volume3d-only", action="store_true",
+                    help="run only the two workload lines in three dimensions (TV and L1 with the 3-D "
+                         "kernel; for profiling their kernels)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the single-slice, uneven-batch and 256-slice lines")
     ap.add_argument("--cpu-sample-slices", type=int, default=16)
@@ -341,6 +344,73 @@ def tv_workload(nz=64, n=256, iters=500, reps=3):
     return out
 
 
+# weighted TV model in three dimensions: algorithmic HBM bytes per slice-pair
+# point (two voxels; FP32, 8 B per complex value).  The exchange holds one
+# plane per slice, so each in-place plane transform (F_y, F_y^-1) reads and
+# writes two planes (32); the z-view transform reads and writes them and
+# reads the 3-D D table (2 x 4 B) (40); the dual row kernel reads two
+# exchange planes, p, W, delta, chibar, M, q_x, q_y, q_z and writes p, q_x,
+# q_y, q_z and two planes (128); the primal row kernel reads two planes, chi,
+# q_x, q_y, q_z, M and writes chi, chibar and two planes (88).  Per
+# voxel-iteration: (2 x (32 + 40 + 32) + 128 + 88) / 2 = 212 B.
+TV3_BYTES_PER_VOXEL_IT = 212.0
+TV3_BYTES_PER_POINT = {"plane_column": 32.0, "z_transform": 40.0, "tv_row": 108.0}
+
+# L1 model with the 3-D kernel (unpacked planes, one slice per complex plane),
+# per plane point (one voxel): in-place plane transforms 16; z-view dual prox
+# reads ex, Yhat, F delta, D and writes Yhat, ex (44); row kernel reads ex and
+# chi and writes both (32).  Per voxel-iteration 16 + 44 + 16 + 32 = 108 B.
+L1_3D_BYTES_PER_VOXEL_IT = 108.0
+L1_3D_BYTES_PER_POINT = {"plane_column": 16.0, "z_transform": 44.0, "plane_row": 32.0}
+
+
+def tv3_workload(nz=64, n=256, iters=500, reps=3, dz=2.0):
+    """The weighted TV model in three dimensions (3-D gradient, 3-D dipole
+    kernel) on nz slices of n x n: wall time per solve and each kernel
+    class's HIP-event time and algorithmic bandwidth."""
+    import torch
+    import pd_inputs
+    import paper_2006_09808_amd as pd
+    dev = torch.device("cuda", 0)
+    w = pd_inputs.tv_stack(6200, nz, n, n, max_iter=iters)
+    # steps inside the 3-D bound: max|W| = max|M| = 1, max|D3| = 2/3, 4 + 4 + 4/dz^2
+    w.tau = w.sigma = 0.95 / np.sqrt((2.0 / 3.0) ** 2 + 8.0 + 4.0 / dz ** 2)
+    with pd.Solver(arena_bytes=8 << 30, device=0) as s:
+        field = s.apply_kernel(torch.from_numpy(w.chi_true.astype(np.float32)).to(dev), kernel="dipole3d",
+                               voxel_z=dz)
+        d = torch.from_numpy(pd_inputs.make_delta(field.cpu().numpy().astype(np.float64), w.eta, w.rho)
+                             .astype(np.float32)).to(dev)
+        W = torch.from_numpy(w.weight.astype(np.float32)).to(dev)
+        M = torch.from_numpy(w.mask.astype(np.float32)).to(dev)
+        chi = torch.empty_like(d)
+        sp = dict(w.solver_params(), model="tv", weight=W, mask=M, kernel="dipole3d", voxel_z=dz)
+        best = None
+        for i in range(reps + 2):
+            t0 = pd.now()
+            r = s.poll(s.submit([(d, chi, sp)])[0], -1)
+            if r["status"] != pd.PD_OK or r["iterations"] != iters:
+                raise RuntimeError("3-D TV solve failed: %r" % (r,))
+            dt = pd.now() - t0
+            if i >= 2:
+                best = dt if best is None else min(best, dt)
+    with pd.Solver(arena_bytes=8 << 30, device=0, time_kernels=True) as s:
+        s.poll(s.submit([(d, chi, sp)])[0], -1)
+        kt = {name: s.kernel_time(kind) for name, kind in
+              (("plane_column", pd.KIND_TV_COLUMN), ("z_transform", pd.KIND_Z), ("tv_row", pd.KIND_TV_ROW))}
+    vit = nz * n * n * iters
+    out = {"workload": "weighted TV in three dimensions (3-D G, 3-D D), %d slices of %dx%d, %d iterations"
+                       % (nz, n, n, iters),
+           "ms": best * 1e3, "voxel_iterations_per_s": vit / best,
+           "bytes_per_voxel_iteration": TV3_BYTES_PER_VOXEL_IT,
+           "achieved_GBs_wall": TV3_BYTES_PER_VOXEL_IT * vit / best / 1e9, "kernels": {}}
+    for name, (nl, ms, pts) in kt.items():
+        if nl:
+            bpp = TV3_BYTES_PER_POINT[name]
+            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
+                                    "bytes_per_launch": bpp * pts / nl}
+    return out
+
+
 def volume3d_workload(nz=64, n=256, iters=500, reps=3):
     """The 3-D dipole kernel (whole-volume operator, slices coupled) on nz
     slices of n x n: wall time per solve (steps replayed from HIP graphs) and
@@ -372,10 +442,14 @@ def volume3d_workload(nz=64, n=256, iters=500, reps=3):
               (("plane_column", pd.KIND_COLUMN), ("plane_row", pd.KIND_ROW), ("z_transform", pd.KIND_Z))}
     vit = nz * n * n * iters
     out = {"workload": "3-D dipole kernel, %d slices of %dx%d, %d iterations" % (nz, n, n, iters),
-           "ms": best * 1e3, "voxel_iterations_per_s": vit / best, "kernels": {}}
+           "ms": best * 1e3, "voxel_iterations_per_s": vit / best,
+           "bytes_per_voxel_iteration": L1_3D_BYTES_PER_VOXEL_IT,
+           "achieved_GBs_wall": L1_3D_BYTES_PER_VOXEL_IT * vit / best / 1e9, "kernels": {}}
     for name, (nl, ms, pts) in kt.items():
         if nl:
-            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl}
+            bpp = L1_3D_BYTES_PER_POINT[name]
+            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
+                                    "bytes_per_launch": bpp * pts / nl}
     return out
 
 
@@ -436,6 +510,10 @@ def main():
         return
     if a.tv_only:
         print(json.dumps({"tv_256x256x64_500it": tv_workload()}), flush=True)
+        return
+    if a.volume3d_only:
+        print(json.dumps({"tv3_256x256x64_500it": tv3_workload(),
+                          "dipole3d_256x256x64_500it": volume3d_workload()}), flush=True)
         return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path to measure "
@@ -582,6 +660,7 @@ def main():
         out["workloads"] = other_workloads()
         out["workloads"]["tv_256x256x64_500it"] = tv_workload()
         out["workloads"]["dipole3d_256x256x64_500it"] = volume3d_workload()
+        out["workloads"]["tv3_256x256x64_500it"] = tv3_workload()
     if a.serve_seconds > 0:
         out["serving"] = serving(a.serve_rate, a.serve_seconds, a.serve_arena_gb)
     if a.serve_seconds > 0 and a.serve_stress_seconds > 0:

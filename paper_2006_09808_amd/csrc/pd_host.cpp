@@ -219,6 +219,11 @@ int rows_per_wg(int nx, int ny, int precision) {
   int s = row_group_big(nx);
   return (ny % s == 0) ? s : 8;
 }
+int col_group_wide(int ny) {   // the widest instantiated FP32 column strip (> 16 only for ny <= 128)
+  int s = 16;
+  while (s < 64 && 2 * s * ny <= 4096) s *= 2;
+  return s;
+}
 int cols_per_wg(int nx, int ny, int precision) {
   if (precision == PD_FP64 || axis_blue(ny) || ny > 512) return 8;
   return (nx % 16 == 0) ? 16 : 8;
@@ -226,8 +231,9 @@ int cols_per_wg(int nx, int ny, int precision) {
 
 // instantiated tile sizes of the two-launch kernels: FP32 plain transforms
 // over whole tiles have rows per row-kernel workgroup in {8, default} and
-// columns per column-kernel workgroup in {8, 16} (8 for columns of 768);
-// every other case (FP64, Bluestein, partial last tile) has tiles of 8
+// columns per column-kernel workgroup in {8, 16, wide} (wide: 32 or 64 for
+// columns of at most 128; 8 only for columns of 768); every other case (FP64,
+// Bluestein, partial last tile) has tiles of 8
 bool rows_valid(int r, int nx, int ny, int precision) {
   if (r <= 0) return false;
   if (precision == PD_FP64 || axis_blue(nx) || ny % r) return r == 8;
@@ -236,7 +242,15 @@ bool rows_valid(int r, int nx, int ny, int precision) {
 bool cols_valid(int cl, int nx, int ny, int precision) {
   if (cl <= 0) return false;
   if (precision == PD_FP64 || axis_blue(ny) || ny > 512 || nx % cl) return cl == 8;
-  return cl == 8 || cl == 16;
+  return cl == 8 || cl == 16 || cl == col_group_wide(ny);
+}
+// strip width of the 3-D kernel's z view (nx ny columns of length nz): the
+// widest instantiated one that tiles the columns, so short z transforms get
+// enough points per workgroup
+int zcols_of(int nx, int ny, int nz, int precision) {
+  for (int w : {col_group_wide(nz), 16})
+    if (cols_valid(w, nx * ny, nz, precision)) return w;
+  return 8;
 }
 
 struct Layout {
@@ -252,7 +266,7 @@ struct Layout {
   bool unpacked;                    // 3-D kernel, L1 model: one slice per plane, P = nz
   bool tv3;                         // 3-D kernel, TV model: pairs, exchange of nz planes
   int planes;                       // planes of the exchange buffer (column kernels' "pairs")
-  int zgroups, ext_z;               // 3-D kernel: z-transform workgroups, kernel variant
+  int zgroups, ext_z, zcols;        // 3-D kernel: z-transform workgroups, kernel variant, strip width
 };
 
 Layout layout_of(const pd_request& r, int precision) {
@@ -264,8 +278,9 @@ Layout layout_of(const pd_request& r, int precision) {
   L.planes = L.tv3 ? r.nz : L.P;
   if (r.kernel == PD_KERNEL_DIPOLE_3D) {
     // z transforms: strips of 8 of the nx ny columns of the [nz][ny nx] view
-    L.zgroups = ceil_div(r.nx * r.ny, 8);
-    L.ext_z = axis_ext(r.nz, r.nx * r.ny, 8);
+    L.zcols = zcols_of(r.nx, r.ny, r.nz, precision);
+    L.zgroups = ceil_div(r.nx * r.ny, L.zcols);
+    L.ext_z = axis_ext(r.nz, r.nx * r.ny, L.zcols);
   }
   L.rows = rows_per_wg(r.nx, r.ny, precision);
   L.cols = cols_per_wg(r.nx, r.ny, precision);
@@ -866,7 +881,7 @@ hipError_t launch_setup(pd_ctx* c, const std::vector<Job*>& js) {
       e = launch_col(axis_phys(j->req.ny), COL_FWD, j->L.cols, P * j->L.col_groups, j->L.col_groups, c->d_vols, rg,
                      1, c->d_ctl, -1, c->precision, j->L.ext_col, c->stream);
       if (e != hipSuccess) return e;
-      e = launch_col(axis_phys(j->req.nz), COL_SETUP, 8, j->L.zgroups, j->L.zgroups, c->d_vols + c->zoff, rg, 1,
+      e = launch_col(axis_phys(j->req.nz), COL_SETUP, j->L.zcols, j->L.zgroups, j->L.zgroups, c->d_vols + c->zoff, rg, 1,
                      c->d_ctl, 0, c->precision, j->L.ext_z, c->stream);
       if (e != hipSuccess) return e;
       e = launch_zero(c->arena.ptr(j->off) + j->L.off_ex, j->L.field, c->stream);
@@ -968,7 +983,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     int px, py, er, ec;                      // transform lengths and kernel variants (row, column)
     int planx, plany;                        // pass plans of the row and column transforms
     bool z3;                                 // 3-D kernel: planes plus the z view
-    int pz, ez, zg, z_off, nzr;              // z: transform length, variant, groups per volume, ranges
+    int pz, ez, zg, zc, z_off, nzr;          // z: transform length, variant, groups per volume, strip, ranges
     int team;
     const ResidentVariant* rv;
     bool multi;                              // multi-shape resident launch (team table at range_off)
@@ -1119,6 +1134,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
         Job* j0 = g.second.front();
         L.z3 = true;
         L.zg = j0->L.zgroups;
+        L.zc = j0->L.zcols;
         L.pz = axis_phys(j0->req.nz);
         L.ez = j0->L.ext_z;
         L.z_off = (int)k;
@@ -1318,7 +1334,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
                                 it, c->precision, L.ec, c->stream);
             };
             auto zk = [&] {
-              return launch_col(L.pz, COL_TV, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
+              return launch_col(L.pz, COL_TV, L.zc, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
                                 c->precision, L.ez, c->stream);
             };
             auto cinv = [&] {
@@ -1349,7 +1365,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
                                 it, c->precision, L.ec, c->stream);
             };
             auto zk = [&] {
-              return launch_col(L.pz, COL_ITER, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
+              return launch_col(L.pz, COL_ITER, L.zc, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, rz, L.nzr, c->d_ctl, it,
                                 c->precision, L.ez, c->stream);
             };
             auto cinv = [&] {
@@ -1400,7 +1416,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
             r = launch_col(L.py, COL_FWD_CHK, L.cols, L.ncolp * L.cg, L.cg, c->d_vols, rcol, L.nranges, c->d_ctl,
                            K - 1, c->precision, L.ec, c->stream);
             if (r != hipSuccess) return r;
-            r = launch_col(L.pz, COL_CHECK, 8, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, c->d_ranges + L.z_off,
+            r = launch_col(L.pz, COL_CHECK, L.zc, L.nzr * L.zg, L.zg, c->d_vols + c->zoff, c->d_ranges + L.z_off,
                            L.nzr, c->d_ctl, K - 1, c->precision, L.ez, c->stream);
             if (r != hipSuccess) return r;
             continue;
@@ -1435,7 +1451,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
         continue;
       }
       sig += "|" + std::string(L.tv ? "tv" : "l1") + (L.z3 ? "z" + std::to_string(L.pz) + "," + std::to_string(L.zg) + "," +
-                                                                std::to_string(L.z_off) + "," + std::to_string(L.nzr)
+                                                                std::to_string(L.z_off) + "," + std::to_string(L.nzr) + "," + std::to_string(L.zc)
                                                           : std::string()) +
              std::to_string(L.nx) + "," + std::to_string(L.ny) + "," + std::to_string(L.rows) + "," +
              std::to_string(L.cols) + "," + std::to_string(L.npairs) + "," + std::to_string(L.nranges) + "," +
@@ -1823,7 +1839,7 @@ pd_status apply_kernel(pd_ctx* c, const pd_request* r, bool noalloc) {
         e = launch_col(axis_phys(r->ny), COL_FWD, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
                        c->d_ctl, -1, c->precision, j.L.ext_col, c->stream);
       if (e == hipSuccess)
-        e = launch_col(axis_phys(r->nz), COL_APPLY, 8, j.L.zgroups, j.L.zgroups, c->d_vols + c->zoff, dr, 1,
+        e = launch_col(axis_phys(r->nz), COL_APPLY, j.L.zcols, j.L.zgroups, j.L.zgroups, c->d_vols + c->zoff, dr, 1,
                        c->d_ctl, 0, c->precision, j.L.ext_z, c->stream);
       if (e == hipSuccess)
         e = launch_col(axis_phys(r->ny), COL_INV, j.L.cols, P * j.L.col_groups, j.L.col_groups, c->d_vols, dr, 1,
@@ -2220,7 +2236,8 @@ pd_status pd_tune(pd_ctx* c, int nx, int ny, int nz, int iters, pd_tune_entry* e
     // independent; an iteration runs one of each)
     const int rg0 = ceil_div(ny, rows_per_wg(nx, ny, c->precision));
     const int cg0 = ceil_div(nx, cols_per_wg(nx, ny, c->precision));
-    for (int cols : {8, 16}) {
+    const int wide = col_group_wide(ny);
+    for (int cols : {8, 16, wide > 16 ? wide : 0}) {
       if (e != hipSuccess) break;
       if (!cols_valid(cols, nx, ny, c->precision)) continue;
       const int cg = ceil_div(nx, cols);

@@ -577,13 +577,23 @@ constexpr int row_s_big(int n) {
   return s;
 }
 
+// widest column strip for length-N columns (FP32): the largest power of two
+// with at most 4096 points per workgroup, clamped to [16, 64]; wider than 16
+// only for N <= 128 (short transforms, e.g. along z)
+constexpr int col_s_wide(int n) {
+  int s = 16;
+  while (s < 64 && 2 * s * n <= 4096) s *= 2;
+  return s;
+}
+
 }  // namespace pdk
 
 // Defines launch_col_<N> / launch_row_<N>: transforms of length N, tile
 // width `cols` / `rows`, EXT `ext` (0: plain; 1: partial last tile; 2:
 // Bluestein transforms of any length <= (N + 1) / 2 on length-N transforms),
 // pass plan `plan` (FP32 whole tiles only; 0 elsewhere).  FP32 EXT 0 has two
-// tile sizes; every other combination uses tiles of 8.
+// tile sizes (three columns wide for N <= 128); every other combination uses
+// tiles of 8.
 #define PD_INSTANTIATE(N)                                                                         \
   namespace pdk {                                                                                 \
   hipError_t launch_col_##N(int mode, int cols, int grid, int groups, const Vol* vols,            \
@@ -597,6 +607,9 @@ constexpr int row_s_big(int n) {
     }                                                                                             \
     if (ext == 0 && cols == 16 && N <= 512)                                                       \
       return launch_col_plan<N, (N <= 512 ? 16 : 8)>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
+    constexpr int SW = col_s_wide(N);                                                             \
+    if (SW > 16 && ext == 0 && cols == SW)                                                        \
+      return launch_col_plan<N, SW>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     if (ext == 0 && cols == 8)                                                                    \
       return launch_col_plan<N, 8>(plan, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
     if (cols == 8) return launch_col_x<N, float, 8>(ext, mode, grid, groups, vols, ranges, nranges, ctl, it, st); \
