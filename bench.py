@@ -49,9 +49,9 @@ def parse():
                     help="force this resident-kernel variant instead of the autotuned choice")
     ap.add_argument("--tv-only", action="store_true",
                     help="run only the weighted-TV workload line (for profiling its kernels)")
-    ap.add_argument("--volume3d-only", action="store_true",
-                    help="run only the two workload lines in three dimensions (TV and L1 with the 3-D "
-                         "kernel; for profiling their kernels)")
+    ap.add_argument("--volume3d-only", nargs="?", const="both", choices=("both", "tv", "l1"),
+                    help="run only the workload lines in three dimensions (the TV model, the L1 model with "
+                         "the 3-D kernel, or both; for profiling their kernels)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the single-slice, uneven-batch and 256-slice lines")
     ap.add_argument("--cpu-sample-slices", type=int, default=16)
@@ -512,8 +512,12 @@ def main():
         print(json.dumps({"tv_256x256x64_500it": tv_workload()}), flush=True)
         return
     if a.volume3d_only:
-        print(json.dumps({"tv3_256x256x64_500it": tv3_workload(),
-                          "dipole3d_256x256x64_500it": volume3d_workload()}), flush=True)
+        out = {}
+        if a.volume3d_only in ("both", "tv"):
+            out["tv3_256x256x64_500it"] = tv3_workload()
+        if a.volume3d_only in ("both", "l1"):
+            out["dipole3d_256x256x64_500it"] = volume3d_workload()
+        print(json.dumps(out), flush=True)
         return
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path to measure "
