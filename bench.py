@@ -301,6 +301,12 @@ def other_workloads(reps=20):
 TV_BYTES_PER_VOXEL_IT = 96.0
 TV_COL_BYTES_PER_POINT = 16.0
 TV_ROW_BYTES_PER_POINT = 80.0       # mean of the dual (96) and primal (64) row kernels
+# the TV model's resident launch (square slices): the exchange field stays in
+# the L2 of the team's XCD, so per iteration HBM sees the row phases' state
+# only: dual reads p, W, delta, chibar, M, q_x, q_y and writes p, q_x, q_y
+# (80); primal reads chi, q_x, q_y, M and writes chi, chibar (48): 128 B per
+# slice-pair point, 64 B per voxel-iteration
+TV_RES_BYTES_PER_POINT_IT = 128.0
 
 
 def tv_workload(nz=64, n=256, iters=500, reps=3):
@@ -328,19 +334,46 @@ def tv_workload(nz=64, n=256, iters=500, reps=3):
             dt = pd.now() - t0
             if i >= 2:
                 best = dt if best is None else min(best, dt)
-    with pd.Solver(arena_bytes=4 << 30, device=0, time_kernels=True) as s:
-        s.poll(s.submit([(d, chi, sp)])[0], -1)
-        kt = {name: s.kernel_time(kind) for name, kind in (("tv_column", pd.KIND_TV_COLUMN), ("tv_row", pd.KIND_TV_ROW))}
+    # the four-launch path on the same input, for comparison
+    with pd.Solver(arena_bytes=4 << 30, device=0, resident=False) as s:
+        best4 = None
+        for i in range(reps + 2):
+            t0 = pd.now()
+            r = s.poll(s.submit([(d, chi, sp)])[0], -1)
+            if r["status"] != pd.PD_OK or r["iterations"] != iters:
+                raise RuntimeError("TV solve failed: %r" % (r,))
+            dt = pd.now() - t0
+            if i >= 2:
+                best4 = dt if best4 is None else min(best4, dt)
+    kt = {}
+    for resident in (True, False):
+        with pd.Solver(arena_bytes=4 << 30, device=0, time_kernels=True, resident=resident) as s:
+            s.poll(s.submit([(d, chi, sp)])[0], -1)
+            kinds = (("tv_resident", pd.KIND_TV_RESIDENT),) if resident else \
+                (("tv_column", pd.KIND_TV_COLUMN), ("tv_row", pd.KIND_TV_ROW))
+            kt.update({name: s.kernel_time(kind) for name, kind in kinds})
     vit = nz * n * n * iters
     out = {"workload": "weighted TV (Eq. (1)), %d slices of %dx%d, %d iterations" % (nz, n, n, iters),
            "ms": best * 1e3, "voxel_iterations_per_s": vit / best,
-           "bytes_per_voxel_iteration": TV_BYTES_PER_VOXEL_IT,
-           "achieved_GBs_wall": TV_BYTES_PER_VOXEL_IT * vit / best / 1e9, "kernels": {}}
+           "path": "resident launch (one per step)",
+           "hbm_bytes_per_voxel_iteration": TV_RES_BYTES_PER_POINT_IT / 2,
+           "achieved_GBs_wall": TV_RES_BYTES_PER_POINT_IT / 2 * vit / best / 1e9,
+           "four_launch": {"ms": best4 * 1e3, "voxel_iterations_per_s": vit / best4,
+                           "bytes_per_voxel_iteration": TV_BYTES_PER_VOXEL_IT,
+                           "achieved_GBs_wall": TV_BYTES_PER_VOXEL_IT * vit / best4 / 1e9},
+           "kernels": {}}
     for name, (nl, ms, pts) in kt.items():
-        if nl:
-            bpp = TV_COL_BYTES_PER_POINT if name == "tv_column" else TV_ROW_BYTES_PER_POINT
-            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
-                                    "bytes_per_launch": bpp * pts / nl, "traffic": measured_traffic(name)[0]}
+        if not nl:
+            continue
+        if name == "tv_resident":
+            # pts counts iterations x pair points
+            out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl,
+                                    "GBs": TV_RES_BYTES_PER_POINT_IT * pts / (ms * 1e-3) / 1e9,
+                                    "bytes_per_launch": TV_RES_BYTES_PER_POINT_IT * pts / nl}
+            continue
+        bpp = TV_COL_BYTES_PER_POINT if name == "tv_column" else TV_ROW_BYTES_PER_POINT
+        out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
+                                "bytes_per_launch": bpp * pts / nl, "traffic": measured_traffic(name)[0]}
     return out
 
 

@@ -92,8 +92,9 @@ enum { PD_MODEL_L1 = 0, PD_MODEL_TV = 1 };
 enum {
   PD_FLAG_TIME_KERNELS = 1,  /* time every launch of the iteration kernels with
                                 HIP events on the context stream (pd_kernel_time) */
-  PD_FLAG_NO_RESIDENT = 2,   /* never use the resident multi-iteration kernel:
-                                two launches per iteration for every shape     */
+  PD_FLAG_NO_RESIDENT = 2,   /* never use the resident multi-iteration kernels
+                                (L1 and TV models): two launches per iteration
+                                for every shape (four for the TV model)        */
   PD_FLAG_FENCED_EXCHANGE = 4, /* resident kernel: always exchange between the
                                 workgroups of a team with agent-scope
                                 release/acquire (L2 write-back), even when
@@ -291,7 +292,10 @@ double pd_now(void);
  * transforms), 6 = multi-shape resident launches (a whole step of the pairs
  * of several square shapes in one launch: 64x64, 128x128 and 256x256 volumes
  * whose chosen resident variant runs the default FFT plan, whenever a step
- * holds two or more such shapes).  pd_kernel_time_reset clears all. */
+ * holds two or more such shapes), 7 = the TV model's resident launches (a
+ * whole step of iterations of square 64x64, 128x128 or 256x256 TV volumes:
+ * the column halves of the transforms on chip, the state streamed from HBM).
+ * pd_kernel_time_reset clears all. */
 pd_status pd_kernel_time(pd_ctx* c, int kind, int64_t* launches, double* total_ms, double* point_iters);
 pd_status pd_kernel_time_reset(pd_ctx* c);
 

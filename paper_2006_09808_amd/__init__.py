@@ -12,6 +12,6 @@ from .pdlib import (  # noqa: F401
     PD_OK, PD_PENDING, PD_ERR_ARG, PD_ERR_SIZE, PD_ERR_STEP, PD_ERR_BUDGET,
     PD_ERR_NONFINITE, PD_ERR_HIP, PD_ERR_CANCELLED, PD_ERR_TICKET, PD_ERR_NODEVICE, PD_ERR_SCRATCH,
     PD_STATIC_SCRATCH_BYTES, PD_FLAG_TEST_BARRIER_GIVEUP,
-    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z, KIND_MULTI,
+    PD_FP32, PD_FP64, KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z, KIND_MULTI, KIND_TV_RESIDENT,
     PD_FLAG_NO_RESIDENT, PD_MODEL_L1, PD_MODEL_TV, PD_KERNEL_DIPOLE_3D,
 )

@@ -555,7 +555,8 @@ struct pd_ctx {
   // kernel timing
   bool time_kernels = false;
   std::mutex tmu;
-  static constexpr int kKinds = 7;        // column, row, resident, TV column, TV row, 3-D z transform, multi-shape resident
+  static constexpr int kKinds = 8;        // column, row, resident, TV column, TV row, 3-D z transform,
+                                          // multi-shape resident, TV resident
   int64_t t_launches[kKinds] = {};
   double t_ms[kKinds] = {};
   double t_points[kKinds] = {};           // iterations x slice-pair points processed
@@ -1010,6 +1011,14 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
                ? resident_variant(nx, tn.res_variant)
                : nullptr;
   };
+  // The TV model's resident launch for a 2-D TV group, or null for its
+  // four-launch path.
+  auto tv_rv = [&](const GroupKey& gk) -> const ResidentVariant* {
+    return (c->precision == PD_FP32 && !(c->cfg.flags & PD_FLAG_NO_RESIDENT) && gk.nx == gk.ny &&
+            gk.model == PD_MODEL_TV && gk.nz3 == 0 && !c->no_resident.count({gk.nx, gk.ny}))
+               ? resident_tv_variant(gk.nx)
+               : nullptr;
+  };
   // Several resident shapes whose chosen variants' (shape, FFT plan) is a
   // body of the multi-shape launch share it (a body gives the same bits as
   // every variant of its plan), if their teams fit the range table.
@@ -1044,9 +1053,9 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
     const bool z3 = g.first.nz3 > 0;
     if (!multi_jobs.empty() && std::find(multi_jobs.begin(), multi_jobs.end(), g.second.front()) != multi_jobs.end())
       continue;   // in the multi-shape launches below
-    const ResidentVariant* rv = chosen_rv(g.first);
+    const ResidentVariant* rv = tv ? tv_rv(g.first) : chosen_rv(g.first);
     int maxt = rv ? std::min(rv->max_teams(), kMaxTeamSlots) : 0;
-    if (rv) {
+    if (rv && !tv) {
       // the chosen variant was timed at some slice count; when this step's
       // pairs need more than one of its co-resident launches, take the
       // variant of the same FFT plan with the most co-resident teams instead
@@ -1072,6 +1081,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       L.nx = nx;
       L.ny = ny;
       L.resident = true;
+      L.tv = tv;
       L.team = team;
       L.rv = rv;
       L.range_off = (int)k;
@@ -1301,7 +1311,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
         return L.rv->launch(L.npairs, c->d_vols, rr, L.nranges, c->d_ctl, c->d_counters, c->d_abort, fenced,
                             c->spin_limit, c->stream);
       };
-      r = with_events ? timed(2, pts, res) : res();
+      r = with_events ? timed(L.tv ? 7 : 2, pts, res) : res();
       if (r != hipSuccess) return r;
     }
     return hipSuccess;
@@ -1445,7 +1455,7 @@ hipError_t enqueue_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool 
       }
       if (L.resident) {
         // the variant (its kernel: shape, team, block size and FFT plan) and its arguments
-        sig += "|r" + std::to_string(L.nx) + "," + std::to_string(L.rv->team()) + "," +
+        sig += "|r" + std::string(L.tv ? "tv" : "") + std::to_string(L.nx) + "," + std::to_string(L.rv->team()) + "," +
                std::to_string(L.rv->threads()) + "," + std::to_string(L.rv->plan()) + "," +
                std::to_string(L.npairs) + "," + std::to_string(L.range_off) + "," + std::to_string(L.nranges);
         continue;

@@ -233,5 +233,9 @@ hipError_t launch_resident_multi(int quota, const Vol* vols, const Range* table,
 
 int resident_variant_count(int n);                      // 0: no resident kernel for n x n
 const ResidentVariant* resident_variant(int n, int v);  // nullptr if out of range
+// The weighted TV model's resident launch of square n x n slices (one
+// variant per shape; nullptr: none for n).  Same arguments and protocol as
+// the L1 model's; the volumes' descriptors carry the TV state.
+const ResidentVariant* resident_tv_variant(int n);
 
 }  // namespace pdk

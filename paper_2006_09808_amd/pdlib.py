@@ -24,7 +24,7 @@ _KERNELS = {"dipole": PD_KERNEL_DIPOLE, "identity": PD_KERNEL_IDENTITY, "dipole3
 PD_MODEL_L1, PD_MODEL_TV = 0, 1
 PD_FLAG_TIME_KERNELS, PD_FLAG_NO_RESIDENT, PD_FLAG_FENCED_EXCHANGE, PD_FLAG_NO_GRAPHS = 1, 2, 4, 8
 PD_FLAG_TEST_BARRIER_GIVEUP = 16
-KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z, KIND_MULTI = 0, 1, 2, 3, 4, 5, 6
+KIND_COLUMN, KIND_ROW, KIND_RESIDENT, KIND_TV_COLUMN, KIND_TV_ROW, KIND_Z, KIND_MULTI, KIND_TV_RESIDENT = range(8)
 
 # lengths with a direct FFT plan; any other length 2..MAX_BLUESTEIN runs
 # through the Bluestein (chirp-z) engine

@@ -396,6 +396,8 @@ const ResidentVariant* resident_variant(int n, int v) {
     if (r.n == n && v-- == 0) return &r;
   return nullptr;
 }
+// the scenarios here submit no TV-model requests
+const ResidentVariant* resident_tv_variant(int) { return nullptr; }
 
 }  // namespace pdk
 

@@ -180,3 +180,75 @@ def test_tv_repeated_solves_are_bitwise_equal(solver, torch_mod):
         outs.append(chi)
     np.testing.assert_array_equal(outs[0], outs[1])
     np.testing.assert_array_equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+# the resident launch of the TV model (square 64², 128², 256² slices)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def solver_two(torch_mod):
+    import paper_2006_09808_amd as pd
+    s = pd.Solver(arena_bytes=4 << 30, device=0, resident=False)
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("case", [(91, 3, 64, 64, 40), (92, 5, 128, 128, 33), (93, 2, 256, 256, 25),
+                                  (94, 7, 256, 256, 12)], ids=lambda c: "%d-%d-%d" % (c[2], c[3], c[1]))
+def test_tv_resident_matches_four_launch_path_and_oracle(solver, solver_two, torch_mod, case):
+    """Square TV volumes of 64², 128² and 256² run as one resident launch per
+    step.  Its tiles give every transform the arithmetic of the four-launch
+    path's default tiles, and the updates are the same expressions, so the
+    two paths agree bitwise, and both meet the oracle's bar."""
+    import paper_2006_09808_amd as pd
+    seed, nz, ny, nx, iters = case
+    w, delta, W, M = make_tv_case(seed, nz, ny, nx, iters=iters)
+    sp = w.solver_params()
+    chi_r, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
+    chi_t, info_t = gpu_tv_solve(solver_two, torch_mod, delta, W, M, **sp)
+    assert info["status"] == info_t["status"] == 0 and info["iterations"] == info_t["iterations"] == iters
+    _say("  resident vs four-launch: relL2 %.3e, bitwise %s" % (rel_l2(chi_r, chi_t), np.array_equal(chi_r, chi_t)))
+    np.testing.assert_array_equal(chi_r, chi_t)
+    ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
+    _parity.check(chi_r, ref, "tv resident chi")
+    with pd.Solver(arena_bytes=1 << 30, device=0, time_kernels=True) as s:
+        gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+        n_res, _, _ = s.kernel_time(pd.KIND_TV_RESIDENT)
+        n_col, _, _ = s.kernel_time(pd.KIND_TV_COLUMN)
+        assert n_res >= 1 and n_col == 0
+
+
+@pytest.mark.timeout(600)
+def test_tv_resident_bench_shape_256x256x64(solver, torch_mod):
+    """The TV workload the benchmark times (64 slices of 256², all 32 pairs in
+    one co-resident launch), a few iterations against the oracle over the
+    whole volume."""
+    w, delta, W, M = make_tv_case(6000, 64, 256, 256, iters=6)
+    sp = w.solver_params()
+    chi, info = gpu_tv_solve(solver, torch_mod, delta, W, M, **sp)
+    assert info["status"] == 0 and info["iterations"] == 6
+    _say("  GPU done; oracle")
+    ref, _ = oracle.solve_tv(delta.astype(np.float64), W.astype(np.float64), M.astype(np.float64), **sp)
+    _parity.check(chi, ref, "tv resident 256x256x64")
+    for z in (0, 1, 62, 63):
+        _parity.check(chi[z:z + 1], ref[z:z + 1], "tv resident slice %d" % z)
+
+
+def test_tv_resident_barrier_giveup_recovers(torch_mod):
+    """A TV resident launch whose team barrier gives up (forced from the host:
+    every barrier gives up at its first wait) restarts its request on the
+    four-launch path; the result equals the unforced run bitwise (the two
+    paths compute the same bits)."""
+    import paper_2006_09808_amd as pd
+    w, delta, W, M = make_tv_case(95, 4, 128, 128, iters=30)
+    sp = w.solver_params()
+    with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+        ref, _ = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+    with pd.Solver(arena_bytes=1 << 30, device=0, barrier_giveup_test=True) as s:
+        got, info = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+        aborted, restarted = s.recovery_stats()
+        _say("  aborted rounds %d, restarted requests %d" % (aborted, restarted))
+        assert info["status"] == 0 and info["iterations"] == 30
+        assert aborted >= 1 and restarted >= 1
+    np.testing.assert_array_equal(got, ref)
