@@ -91,6 +91,8 @@ KERNEL_SOURCES = {
     "resident": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_resident.hpp", "../build.py"),
     "tv_column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "../build.py"),
     "tv_row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_tv_row.hpp", "../build.py"),
+    "tv_resident": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_resident.hpp", "pd_resident_tv.hpp",
+                    "../build.py"),
 }
 # FP32 vector ALU ceilings of MI355X.  Published: 157.3 TFLOP/s, which needs
 # packed FP32 (two FMAs per lane per instruction).  The library is compiled
@@ -367,9 +369,12 @@ def tv_workload(nz=64, n=256, iters=500, reps=3):
             continue
         if name == "tv_resident":
             # pts counts iterations x pair points
+            traffic, src = measured_traffic(name)
             out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl,
                                     "GBs": TV_RES_BYTES_PER_POINT_IT * pts / (ms * 1e-3) / 1e9,
-                                    "bytes_per_launch": TV_RES_BYTES_PER_POINT_IT * pts / nl}
+                                    "bytes_per_launch": TV_RES_BYTES_PER_POINT_IT * pts / nl,
+                                    "traffic": traffic, "traffic_source": src,
+                                    "traffic_GBs": None if traffic is None else traffic / (ms / nl * 1e-3) / 1e9}
             continue
         bpp = TV_COL_BYTES_PER_POINT if name == "tv_column" else TV_ROW_BYTES_PER_POINT
         out["kernels"][name] = {"launches": nl, "avg_ms": ms / nl, "GBs": bpp * pts / (ms * 1e-3) / 1e9,
