@@ -252,3 +252,29 @@ def test_tv_resident_barrier_giveup_recovers(torch_mod):
         assert info["status"] == 0 and info["iterations"] == 30
         assert aborted >= 1 and restarted >= 1
     np.testing.assert_array_equal(got, ref)
+
+
+def test_tv_resident_more_pairs_than_one_launch_and_short_steps(solver_two, torch_mod):
+    """40 slice pairs of 256² (more than one co-resident launch holds: two
+    launches per step) and, on another context, steps of 7 iterations (the
+    state carries over between resident launches in HBM): both equal the
+    four-launch path bitwise."""
+    import paper_2006_09808_amd as pd
+    w, delta, W, M = make_tv_case(96, 80, 256, 256, iters=12)
+    sp = w.solver_params()
+    chi_t, _ = gpu_tv_solve(solver_two, torch_mod, delta, W, M, **sp)
+    with pd.Solver(arena_bytes=8 << 30, device=0, time_kernels=True) as s:
+        chi_r, info = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+        n_res, _, _ = s.kernel_time(pd.KIND_TV_RESIDENT)
+        _say("  80 slices: %d resident launches" % n_res)
+        assert info["status"] == 0 and n_res >= 2
+    np.testing.assert_array_equal(chi_r, chi_t)
+    w, delta, W, M = make_tv_case(97, 6, 128, 128, iters=30)
+    sp = w.solver_params()
+    chi_t, _ = gpu_tv_solve(solver_two, torch_mod, delta, W, M, **sp)
+    with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=7, time_kernels=True) as s:
+        chi_r, info = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+        n_res, _, _ = s.kernel_time(pd.KIND_TV_RESIDENT)
+        _say("  steps of 7: %d resident launches" % n_res)
+        assert info["status"] == 0 and info["iterations"] == 30 and n_res == 5
+    np.testing.assert_array_equal(chi_r, chi_t)
