@@ -531,14 +531,51 @@ def cpu_baseline(w, nslices, iters):
     # for the oracle, so its GPU result is checked whole
     w1 = pd_inputs.config1()
     d1 = pd_inputs.make_delta(oracle.forward(w1.chi_true), w1.eta, w1.rho).astype(np.float32)
+    t1 = time.perf_counter()
     ref1, _ = oracle.solve(d1.astype(np.float64), **w1.solver_params())
+    t1 = time.perf_counter() - t1
     with pd.Solver(arena_bytes=256 << 20, device=0) as s:
         got1, info1 = s.solve(torch.from_numpy(d1).to("cuda:0"), **w1.solver_params())
     got1 = got1.cpu().numpy().astype(np.float64)
     out["parity_single_64x64x1_200it"] = {
         "relL2": float(np.linalg.norm(got1 - ref1) / np.linalg.norm(ref1)),
         "max_abs_ppm": float(np.abs(got1 - ref1).max()), "tolerance": 1e-4, "iterations": info1["iterations"]}
+    out["per_config"] = oracle_per_config(t1, w1)
     return out
+
+
+def oracle_per_config(t1, w1):
+    """The oracle's rate on bounded samples of the other workloads (same
+    host, same threads): the single 64x64 slice whole, one slice pair of each
+    volume size of the uneven batch, two slices of the tilted-needle volume;
+    fixed iteration counts (the oracle's cost per iteration does not depend on
+    the stop rule)."""
+    import oracle
+    import pd_inputs
+    res = {"single_64x64x1_200it": {"value": 64 * 64 * w1.max_iter / t1, "seconds": t1,
+                                    "sample": "the whole workload"}}
+    tot_v, tot_t, parts = 0.0, 0.0, []
+    for w in pd_inputs.config3():
+        nz, ny, nx = w.shape
+        iters = 20 if nx <= 128 else 10
+        d = pd_inputs.make_delta(oracle.forward(w.chi_true[:2]), w.eta[:2], w.rho)
+        t0 = time.perf_counter()
+        oracle.solve(d, lam=w.lam, tau=w.tau, sigma=w.sigma, theta=w.theta, max_iter=iters)
+        dt = time.perf_counter() - t0
+        tot_v += 2 * nx * ny * iters
+        tot_t += dt
+        parts.append("%dx%d: 2 slices x %d iterations" % (nx, ny, iters))
+    res["uneven_128x32_256x48_384x24"] = {"value": tot_v / tot_t, "seconds": tot_t, "sample": "; ".join(parts)}
+    w4 = pd_inputs.config4()
+    d4 = pd_inputs.make_delta(oracle.forward(w4.chi_true[:2]), w4.eta[:2], w4.rho)
+    t0 = time.perf_counter()
+    oracle.solve(d4, **dict(w4.solver_params(), max_iter=20))
+    dt = time.perf_counter() - t0
+    res["precision_256x256x128"] = {"value": 2 * 256 * 256 * 20 / dt, "seconds": dt,
+                                    "sample": "2 of 128 slices, 20 of 800 iterations"}
+    for v in res.values():
+        v["unit"] = "voxel-iterations/s"
+    return res
 
 
 def main():
