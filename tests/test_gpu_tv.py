@@ -195,7 +195,8 @@ def solver_two(torch_mod):
 
 
 @pytest.mark.parametrize("case", [(91, 3, 64, 64, 40), (92, 5, 128, 128, 33), (93, 2, 256, 256, 25),
-                                  (94, 7, 256, 256, 12)], ids=lambda c: "%d-%d-%d" % (c[2], c[3], c[1]))
+                                  (94, 7, 256, 256, 12), (98, 1, 256, 256, 20)],
+                         ids=lambda c: "%d-%d-%d" % (c[2], c[3], c[1]))
 def test_tv_resident_matches_four_launch_path_and_oracle(solver, solver_two, torch_mod, case):
     """Square TV volumes of 64², 128² and 256² run as one resident launch per
     step.  Its tiles give every transform the arithmetic of the four-launch
