@@ -218,6 +218,11 @@ def test_tv_resident_matches_four_launch_path_and_oracle(solver, solver_two, tor
         n_res, _, _ = s.kernel_time(pd.KIND_TV_RESIDENT)
         n_col, _, _ = s.kernel_time(pd.KIND_TV_COLUMN)
         assert n_res >= 1 and n_col == 0
+    # the agent-scope exchange protocol (every barrier writes back and
+    # invalidates L2) gives the same bits
+    with pd.Solver(arena_bytes=1 << 30, device=0, fenced_exchange=True) as s:
+        chi_f, _ = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+    np.testing.assert_array_equal(chi_f, chi_r)
 
 
 @pytest.mark.timeout(600)
