@@ -92,7 +92,7 @@ KERNEL_SOURCES = {
     "tv_column": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "../build.py"),
     "tv_row": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_tv_row.hpp", "../build.py"),
     "tv_resident": ("pd_fft.hpp", "pd_kern_impl.hpp", "pd_internal.hpp", "pd_resident.hpp", "pd_resident_tv.hpp",
-                    "../build.py"),
+                    "pd_resident_tv.hip", "../build.py"),
 }
 # FP32 vector ALU ceilings of MI355X.  Published: 157.3 TFLOP/s, which needs
 # packed FP32 (two FMAs per lane per instruction).  The library is compiled

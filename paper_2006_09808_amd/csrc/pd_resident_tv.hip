@@ -1,13 +1,16 @@
 // The TV model's resident variants (pd_resident_tv.hpp) of the square slice
-// shapes 64x64, 128x128 and 256x256: teams of 4, 8 and 16 workgroups of 256
-// threads (16 rows and 16 columns per member), default FFT plans.  With these
-// tiles every row and column transform is the one the two-launch TV kernels
-// run at their default tiles.
+// shapes 64x64, 128x128 and 256x256: teams of 4 and 8 workgroups of 256
+// threads (16 rows and 16 columns per member) and of 8 workgroups of 512
+// threads (32 rows and columns; 7% faster at 256x256x64 than 16 x 256, while
+// 512-thread members were slower at 64x64 and 128x128), default FFT plans.
+// Every row and column transform is the one the four-launch TV kernels run
+// at the same plan (the rows or columns per workgroup do not change a
+// sequence's arithmetic).
 #include "pd_resident_tv.hpp"
 
 PD_INSTANTIATE_RESIDENT_TV(64, 4, 256, 0)
 PD_INSTANTIATE_RESIDENT_TV(128, 8, 256, 0)
-PD_INSTANTIATE_RESIDENT_TV(256, 16, 256, 0)
+PD_INSTANTIATE_RESIDENT_TV(256, 8, 512, 0)
 
 namespace pdk {
 
