@@ -366,15 +366,43 @@ struct Fft {
     }
   }
 
+  // Rows layout with one radix in every pass and N/Q butterflies per row
+  // dividing the wave: row s belongs to the N/Q consecutive threads from
+  // s N/Q on, inside one wave, in every pass, and its LDS row is touched by
+  // no other wave.  The passes of such a transform then only need the lanes
+  // of one wave ordered (LDS executes a wave's accesses in issue order), not
+  // a workgroup barrier.
+  static constexpr bool uniform_plan() {
+    for (int i = 1; i < Plan<N, PV>::M; ++i)
+      if (Plan<N, PV>::r(i) != Plan<N, PV>::r(0)) return false;
+    return true;
+  }
+  static constexpr bool kWaveLocal = !COLS && uniform_plan() && (N / Plan<N, PV>::r(0)) <= 64 &&
+                                     64 % (N / Plan<N, PV>::r(0)) == 0 && NT % 64 == 0;
+
+  // order the LDS accesses between two passes: the whole workgroup, or with
+  // WL the lanes of each wave (kWaveLocal engines only)
+  template <bool WL>
+  static __device__ __forceinline__ void lds_sync() {
+    if constexpr (WL) {
+      static_assert(kWaveLocal, "wave-local passes need a wave-local engine");
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+
   // a pass after the first: read LDS, twiddle, DFT; if LAST keep the
   // outputs (positions j + r N/Q) in v, else write them back to LDS.
-  template <int DIR, int PI, bool LAST>
+  template <int DIR, int PI, bool LAST, bool WL = false>
   static __device__ __forceinline__ void pass_from_lds(
       cpx<T> (&v)[nq<pass_radix<N, DIR, PV>(PI)>()][pass_radix<N, DIR, PV>(PI)], cpx<T>* lds,
       const cpx<T>* __restrict__ tw, int tid) {
     constexpr int Q = pass_radix<N, DIR, PV>(PI);
     constexpr int P = pass_prod<N, DIR, PV>(PI);
-    __syncthreads();
+    lds_sync<WL>();
 #pragma unroll
     for (int q = 0; q < nq<Q>(); ++q) {
       int w = tid + q * NT;
@@ -385,7 +413,7 @@ struct Fft {
         for (int r = 0; r < Q; ++r) v[q][r] = lds[lidx(s, j + r * (N / Q))];
       }
     }
-    if constexpr (!LAST) __syncthreads();
+    if constexpr (!LAST) lds_sync<WL>();
 #pragma unroll
     for (int q = 0; q < nq<Q>(); ++q) {
       int w = tid + q * NT;
@@ -420,7 +448,9 @@ struct Fft {
   static constexpr int TW_MAX = N;
   static __host__ __device__ constexpr int tw_count(int /*len*/) { return N; }
 
-  template <int DIR>
+  // With WL (kWaveLocal engines) the passes order only each wave's lanes,
+  // and the caller's sync_before_reuse<true>() suffices between transforms.
+  template <int DIR, bool WL = false>
   static __device__ __forceinline__ void run(cpx<T> (&in)[nq<QF<DIR>()>()][QF<DIR>()],
                                              cpx<T> (&out)[nq<QL<DIR>()>()][QL<DIR>()],
                                              cpx<T>* lds, const cpx<T>* __restrict__ tw, int tid,
@@ -437,14 +467,15 @@ struct Fft {
       if constexpr (M == 3) {
         constexpr int Q1 = pass_radix<N, DIR, PV>(1);
         cpx<T> mid[nq<Q1>()][Q1];
-        pass_from_lds<DIR, 1, false>(mid, lds, tw, tid);
+        pass_from_lds<DIR, 1, false, WL>(mid, lds, tw, tid);
       }
-      pass_from_lds<DIR, M - 1, true>(out, lds, tw, tid);
+      pass_from_lds<DIR, M - 1, true, WL>(out, lds, tw, tid);
     }
   }
 
+  template <bool WL = false>
   static __device__ __forceinline__ void sync_before_reuse() {
-    if constexpr (M > 1) __syncthreads();
+    if constexpr (M > 1) lds_sync<WL>();
   }
 
   // position (sequence, element) of register (q, r) of a first/last pass

@@ -132,6 +132,9 @@ struct Resident {
   static constexpr int NQO = FR::template nq<QO>();
   static constexpr int NQA = FC::template nq<QA>();
   static constexpr int NQB = FC::template nq<QB>();
+  // the row transforms of a wave's rows never leave the wave: their passes
+  // need no workgroup barrier (the team barriers still order the phases)
+  static constexpr bool kWL = FR::kWaveLocal;
   static constexpr int kTeam = TEAM;
   static constexpr int kThreadsPerGroup = NT;
   // shared memory of one team member, carved from one byte buffer: the FFT
@@ -354,7 +357,7 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
           for (int r = 0; r < R::QI; ++r) a[q][r] = buf_ld(rex, v, AR::soff(r));
         }
       }
-      FR::template run<+1>(a, b, lds, twx, tid);
+      FR::template run<+1, kWL>(a, b, lds, twx, tid);
       const bool do_check = check && last;
 #pragma unroll
       for (int q = 0; q < R::NQO; ++q)
@@ -380,8 +383,8 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
           }
         }
       if (!(last && final_step)) {
-        FR::sync_before_reuse();
-        FR::template run<-1>(b, a, lds, twx, tid);
+        FR::template sync_before_reuse<kWL>();
+        FR::template run<-1, kWL>(b, a, lds, twx, tid);
 #pragma unroll
         for (int q = 0; q < R::NQI; ++q) {
           unsigned v;
@@ -407,8 +410,8 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
             int s, n;
             if (FR::template pos<R::QO>(tid, q, r, s, n)) chi_g[(unsigned)((r0 + s) * NX + n)] = chi[q][r];
           }
-        FR::sync_before_reuse();
-        FR::template run<-1>(chi, a, lds, twx, tid);
+        FR::template sync_before_reuse<kWL>();
+        FR::template run<-1, kWL>(chi, a, lds, twx, tid);
 #pragma unroll
         for (int q = 0; q < R::NQI; ++q) {
           unsigned v;
