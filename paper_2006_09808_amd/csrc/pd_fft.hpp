@@ -316,6 +316,7 @@ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 template <typename T, int N, int S, int NT, bool COLS, int PV = 0>
 struct Fft {
   static constexpr int kNT = NT;
+  static constexpr int kN = N;
   static constexpr int LDN = N + N / 32 + 1;                 // padded row (rows layout)
   static constexpr int LDS_ELEMS = COLS ? N * (S + 1) : S * LDN;
 

@@ -66,6 +66,58 @@ struct ExAddr {
   }
 };
 
+// The blocked exchange layout of teams whose transforms are all wave-local:
+// columns in groups of G, element (y, x) of the [NYD][*] plane at
+// ((x / G) NYD + y) G + x mod G.  A column-phase wave transforms exactly one
+// group (G columns of N/Q lanes each), so its loads and stores of a pass
+// cover (N/Q) G consecutive elements; a row-phase wave holds G rows, and each
+// of its accesses covers G x G consecutive elements per group.  Element
+// (s, j + r N/Q) of a pass with radix Q: per-thread part (s, j), uniform r.
+template <typename F, int Q, bool COLPHASE, int NYD, int G>
+struct ExBlk {
+  static constexpr int J = F::kN / Q;
+  static_assert(J % G == 0 && 64 % G == 0, "groups of whole lane runs");
+  static __device__ __forceinline__ bool voff(int tid, int q, int s0, unsigned& v) {
+    int w = tid + q * F::kNT, s, j;
+    F::template coords<Q>(w, s, j);
+    if constexpr (COLPHASE) {
+      const int x = s0 + s;
+      v = (unsigned)((((x / G) * NYD + j) * G + x % G) * 8);
+    } else {
+      v = (unsigned)((((j / G) * NYD + s0 + s) * G + j % G) * 8);
+    }
+    return F::template nbutter<Q>() % F::kNT == 0 || w < F::template nbutter<Q>();
+  }
+  static constexpr unsigned soff(int r) {
+    return COLPHASE ? (unsigned)(r * J * G * 8) : (unsigned)(r * J * NYD * 8);
+  }
+};
+
+// Exchange loads / stores of a first or last pass's registers under address
+// map A (ExAddr or ExBlk).
+template <typename A, int NQ, int Q>
+__device__ __forceinline__ void ex_load(cpx<float> (&a)[NQ][Q], __amdgpu_buffer_rsrc_t rs, int tid, int s0) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    unsigned v;
+    if (A::voff(tid, q, s0, v)) {
+#pragma unroll
+      for (int r = 0; r < Q; ++r) a[q][r] = buf_ld(rs, v, A::soff(r));
+    }
+  }
+}
+template <typename A, int NQ, int Q>
+__device__ __forceinline__ void ex_store(const cpx<float> (&a)[NQ][Q], __amdgpu_buffer_rsrc_t rs, int tid, int s0) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    unsigned v;
+    if (A::voff(tid, q, s0, v)) {
+#pragma unroll
+      for (int r = 0; r < Q; ++r) buf_st(rs, v, A::soff(r), a[q][r]);
+    }
+  }
+}
+
 // Arrive at a team barrier and wait for `target` arrivals in total; thread 0
 // only.  Returns false once the spin limit is hit or another workgroup
 // aborted.  A spin limit of 0 gives up at once (a host-set test of the
@@ -118,7 +170,18 @@ struct Resident {
   static constexpr int RT = NY / TEAM;   // rows per workgroup (row phase)
   static constexpr int CT = NX / TEAM;   // columns per workgroup (column phase)
   using FR = Fft<float, NX, RT, NT, false, PV>;   // PV: FFT pass plan of both axes
-  using FC = Fft<float, NY, CT, NT, true, PV>;
+  // Column transforms on the rows engine (each column's butterflies on
+  // consecutive lanes of one wave) when that engine is wave-local on both
+  // axes: then every transform stays inside its wave, and the exchange uses
+  // the blocked layout (ExBlk) within a launch.  Otherwise the column engine
+  // (columns across threads, every pass behind a workgroup barrier) and the
+  // [ny][nx] layout throughout.
+  using FCW = Fft<float, NY, CT, NT, false, PV>;
+  static constexpr int JC = FCW::kWaveLocal ? NY / FCW::template QF<-1>() : 1;   // lanes per column
+  static constexpr int G = 64 / JC;                                               // columns per wave
+  static constexpr bool kBLK = NX == NY && FR::kWaveLocal && FCW::kWaveLocal && JC >= 8 && JC % G == 0 &&
+                               CT % G == 0;
+  using FC = std::conditional_t<kBLK, FCW, Fft<float, NY, CT, NT, true, PV>>;
   static constexpr int LDS = FR::LDS_ELEMS > FC::LDS_ELEMS ? FR::LDS_ELEMS : FC::LDS_ELEMS;
   // row phase: inverse first radix QI (exchange in), inverse last radix QO
   // (chi state; forward first radix)
@@ -138,10 +201,18 @@ struct Resident {
   static constexpr int kTeam = TEAM;
   static constexpr int kThreadsPerGroup = NT;
   // shared memory of one team member, carved from one byte buffer: the FFT
-  // staging area, F delta of the member's columns ([row][column]), the
-  // twiddles of the row (NX) and column (NY) transforms, the barrier flag
+  // staging area, F delta of the member's columns (blocked layout: [column]
+  // [row] with rows padded by 16 entries, so the two column runs of a half
+  // wave fall on different banks; else [row][column]), the twiddles of the
+  // row (NX) and column (NY) transforms, the barrier flag
+  static constexpr int DH_LD = NY + 16;
+  static constexpr int DH_ELEMS = kBLK ? CT * DH_LD : CT * NY;
+  static __device__ __forceinline__ int dhi(int s, int n) {
+    if constexpr (kBLK) return s * DH_LD + n;
+    else return n * CT + s;
+  }
   static constexpr size_t OFF_DH = (size_t)LDS * sizeof(cpx<float>);
-  static constexpr size_t OFF_TW = OFF_DH + (size_t)CT * NY * sizeof(cpx<float>);
+  static constexpr size_t OFF_TW = OFF_DH + (size_t)DH_ELEMS * sizeof(cpx<float>);
   static constexpr size_t OFF_FLAG = OFF_TW + (size_t)(NX + NY) * sizeof(cpx<float>);
   static constexpr size_t SMEM = OFF_FLAG + 16;
 
@@ -286,7 +357,7 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
       if (FC::template pos<R::QB>(tid, q, r, s, n)) {
         const unsigned o = (unsigned)(n * NX + c0 + s);
         yh[q][r] = yh_g[o];
-        dh_s[n * R::CT + s] = dh_g[o];
+        dh_s[R::dhi(s, n)] = dh_g[o];
         dk[q][r] = dtab[o];
       }
     }
@@ -298,6 +369,15 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
   const __amdgpu_buffer_rsrc_t rex2 = buf_rsrc(ex2, (unsigned)(plane * sizeof(cpx<T>)));
   using AC = ExAddr<FC, R::QA, true, NY, NX>;    // column phase, forward first / inverse last pass
   using AR = ExAddr<FR, R::QI, false, NX, NX>;   // row phase, inverse first / forward last pass
+  // Blocked layout (kBLK) inside a launch; a launch still takes and leaves
+  // the exchange in the [ny][nx] layout every other kernel uses.  The field
+  // is rewritten in place, so one extra team barrier before the first
+  // blocked store (every member has read the [ny][nx] input) and one before
+  // the last iteration's [ny][nx] stores (every member has read the blocked
+  // field).
+  constexpr bool BLK = R::kBLK;
+  using ACB = ExBlk<FC, R::QA, true, NY, R::G>;
+  using ARB = ExBlk<FR, R::QI, false, NY, R::G>;
 
   unsigned phase = 0;
   bool ok = true;
@@ -308,15 +388,13 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
     {
       cpx<T> a[R::NQA][R::QA];
       cpx<T> b[R::NQB][R::QB];
-#pragma unroll
-      for (int q = 0; q < R::NQA; ++q) {
-        unsigned v;
-        if (AC::voff(tid, q, c0, v)) {
-#pragma unroll
-          for (int r = 0; r < R::QA; ++r) a[q][r] = buf_ld(rex, v, AC::soff(r));
-        }
+      if constexpr (BLK) {
+        if (it > 0) ex_load<ACB>(a, rex, tid, c0);
+        else ex_load<AC>(a, rex, tid, c0);
+      } else {
+        ex_load<AC>(a, rex, tid, c0);
       }
-      FC::template run<-1>(a, b, lds, twy, tid);
+      FC::template run<-1, BLK>(a, b, lds, twy, tid);
 #pragma unroll
       for (int q = 0; q < R::NQB; ++q)
 #pragma unroll
@@ -324,7 +402,7 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
           int s, n;
           if (FC::template pos<R::QB>(tid, q, r, s, n)) {
             T d = dk[q][r];
-            cpx<T> y = yh[q][r], e = dh_s[n * R::CT + s];
+            cpx<T> y = yh[q][r], e = dh_s[R::dhi(s, n)];
             cpx<T> yn = mk((y.x + sig * (d * b[q][r].x - e.x)) * inv1ps,
                            (y.y + sig * (d * b[q][r].y - e.y)) * inv1ps);
             yh[q][r] = yn;
@@ -332,15 +410,16 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
             b[q][r] = mk(dn * yn.x, dn * yn.y);
           }
         }
-      FC::sync_before_reuse();
-      FC::template run<+1>(b, a, lds, twy, tid);
-#pragma unroll
-      for (int q = 0; q < R::NQA; ++q) {
-        unsigned v;
-        if (AC::voff(tid, q, c0, v)) {
-#pragma unroll
-          for (int r = 0; r < R::QA; ++r) buf_st(rex, v, AC::soff(r), a[q][r]);
+      FC::template sync_before_reuse<BLK>();
+      FC::template run<+1, BLK>(b, a, lds, twy, tid);
+      if constexpr (BLK) {
+        if (it == 0) {
+          ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
+          if (!ok) break;
         }
+        ex_store<ACB>(a, rex, tid, c0);
+      } else {
+        ex_store<AC>(a, rex, tid, c0);
       }
     }
     ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
@@ -349,14 +428,8 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
     {
       cpx<T> a[R::NQI][R::QI];
       cpx<T> b[R::NQO][R::QO];
-#pragma unroll
-      for (int q = 0; q < R::NQI; ++q) {
-        unsigned v;
-        if (AR::voff(tid, q, r0, v)) {
-#pragma unroll
-          for (int r = 0; r < R::QI; ++r) a[q][r] = buf_ld(rex, v, AR::soff(r));
-        }
-      }
+      if constexpr (BLK) ex_load<ARB>(a, rex, tid, r0);
+      else ex_load<AR>(a, rex, tid, r0);
       FR::template run<+1, kWL>(a, b, lds, twx, tid);
       const bool do_check = check && last;
 #pragma unroll
@@ -385,13 +458,17 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
       if (!(last && final_step)) {
         FR::template sync_before_reuse<kWL>();
         FR::template run<-1, kWL>(b, a, lds, twx, tid);
-#pragma unroll
-        for (int q = 0; q < R::NQI; ++q) {
-          unsigned v;
-          if (AR::voff(tid, q, r0, v)) {
-#pragma unroll
-            for (int r = 0; r < R::QI; ++r) buf_st(rex, v, AR::soff(r), a[q][r]);
-          }
+      }
+      if (BLK && last && (!final_step || do_check)) {
+        ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
+        if (!ok) break;
+      }
+      if (!(last && final_step)) {
+        if constexpr (BLK) {
+          if (!last) ex_store<ARB>(a, rex, tid, r0);
+          else ex_store<AR>(a, rex, tid, r0);
+        } else {
+          ex_store<AR>(a, rex, tid, r0);
         }
       }
       if (do_check) {
@@ -412,14 +489,7 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
           }
         FR::template sync_before_reuse<kWL>();
         FR::template run<-1, kWL>(chi, a, lds, twx, tid);
-#pragma unroll
-        for (int q = 0; q < R::NQI; ++q) {
-          unsigned v;
-          if (AR::voff(tid, q, r0, v)) {
-#pragma unroll
-            for (int r = 0; r < R::QI; ++r) buf_st(rex2, v, AR::soff(r), a[q][r]);
-          }
-        }
+        ex_store<AR>(a, rex2, tid, r0);
       }
     }
     if (!last || check) {
@@ -432,15 +502,8 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
     // residual of F chi against F delta, and the dual's norms, per workgroup
     cpx<T> a[R::NQA][R::QA];
     cpx<T> b[R::NQB][R::QB];
-#pragma unroll
-    for (int q = 0; q < R::NQA; ++q) {
-      unsigned v;
-      if (AC::voff(tid, q, c0, v)) {
-#pragma unroll
-        for (int r = 0; r < R::QA; ++r) a[q][r] = buf_ld(rex2, v, AC::soff(r));
-      }
-    }
-    FC::template run<-1>(a, b, lds, twy, tid);
+    ex_load<AC>(a, rex2, tid, c0);   // stored in the [ny][nx] layout above
+    FC::template run<-1, BLK>(a, b, lds, twy, tid);
     double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < R::NQB; ++q)
@@ -449,7 +512,7 @@ __device__ __forceinline__ void Resident<NX, NY, TEAM, NT, PV>::run(unsigned cha
         int s, n;
         if (FC::template pos<R::QB>(tid, q, r, s, n)) {
           T d = dk[q][r];
-          cpx<T> e = dh_s[n * R::CT + s], y = yh[q][r];
+          cpx<T> e = dh_s[R::dhi(s, n)], y = yh[q][r];
           double rx = (double)(d * b[q][r].x - e.x), ry = (double)(d * b[q][r].y - e.y);
           acc[0] += rx * rx + ry * ry;
           acc[1] += (double)y.x * (double)y.x + (double)y.y * (double)y.y;
