@@ -165,23 +165,38 @@ __device__ __forceinline__ bool team_barrier(unsigned* cnt, unsigned target, int
   return *lds_flag != 0;
 }
 
+// The transform engines of a team member that owns NY/TEAM rows and NX/TEAM
+// columns of a slice pair.  Column transforms run on the rows engine (each
+// column's butterflies on consecutive lanes of one wave) when that engine is
+// wave-local on both axes: then every transform stays inside its wave, and
+// the exchange uses the blocked layout (ExBlk) within a launch.  Otherwise
+// the column engine (columns across threads, every pass behind a workgroup
+// barrier) and the [ny][nx] layout throughout.
 template <int NX, int NY, int TEAM, int NT, int PV>
-struct Resident {
+struct TeamAxes {
   static constexpr int RT = NY / TEAM;   // rows per workgroup (row phase)
   static constexpr int CT = NX / TEAM;   // columns per workgroup (column phase)
   using FR = Fft<float, NX, RT, NT, false, PV>;   // PV: FFT pass plan of both axes
-  // Column transforms on the rows engine (each column's butterflies on
-  // consecutive lanes of one wave) when that engine is wave-local on both
-  // axes: then every transform stays inside its wave, and the exchange uses
-  // the blocked layout (ExBlk) within a launch.  Otherwise the column engine
-  // (columns across threads, every pass behind a workgroup barrier) and the
-  // [ny][nx] layout throughout.
   using FCW = Fft<float, NY, CT, NT, false, PV>;
   static constexpr int JC = FCW::kWaveLocal ? NY / FCW::template QF<-1>() : 1;   // lanes per column
   static constexpr int G = 64 / JC;                                               // columns per wave
   static constexpr bool kBLK = NX == NY && FR::kWaveLocal && FCW::kWaveLocal && JC >= 8 && JC % G == 0 &&
                                CT % G == 0;
   using FC = std::conditional_t<kBLK, FCW, Fft<float, NY, CT, NT, true, PV>>;
+  // the row transforms of a wave's rows never leave the wave: their passes
+  // need no workgroup barrier (the team barriers still order the phases)
+  static constexpr bool kWL = FR::kWaveLocal;
+};
+
+template <int NX, int NY, int TEAM, int NT, int PV>
+struct Resident {
+  using AX = TeamAxes<NX, NY, TEAM, NT, PV>;
+  static constexpr int RT = AX::RT;
+  static constexpr int CT = AX::CT;
+  using FR = typename AX::FR;
+  using FC = typename AX::FC;
+  static constexpr int G = AX::G;
+  static constexpr bool kBLK = AX::kBLK;
   static constexpr int LDS = FR::LDS_ELEMS > FC::LDS_ELEMS ? FR::LDS_ELEMS : FC::LDS_ELEMS;
   // row phase: inverse first radix QI (exchange in), inverse last radix QO
   // (chi state; forward first radix)
@@ -195,9 +210,7 @@ struct Resident {
   static constexpr int NQO = FR::template nq<QO>();
   static constexpr int NQA = FC::template nq<QA>();
   static constexpr int NQB = FC::template nq<QB>();
-  // the row transforms of a wave's rows never leave the wave: their passes
-  // need no workgroup barrier (the team barriers still order the phases)
-  static constexpr bool kWL = FR::kWaveLocal;
+  static constexpr bool kWL = AX::kWL;
   static constexpr int kTeam = TEAM;
   static constexpr int kThreadsPerGroup = NT;
   // shared memory of one team member, carved from one byte buffer: the FFT

@@ -49,10 +49,14 @@ __device__ __forceinline__ void st_st(__amdgpu_buffer_rsrc_t r, unsigned voff, c
 
 template <int NX, int NY, int TEAM, int NT, int PV>
 struct ResidentTv {
-  static constexpr int RT = NY / TEAM;   // rows per workgroup (row phases)
-  static constexpr int CT = NX / TEAM;   // columns per workgroup (column phases)
-  using FR = Fft<float, NX, RT, NT, false, PV>;
-  using FC = Fft<float, NY, CT, NT, true, PV>;
+  using AX = TeamAxes<NX, NY, TEAM, NT, PV>;
+  static constexpr int RT = AX::RT;   // rows per workgroup (row phases)
+  static constexpr int CT = AX::CT;   // columns per workgroup (column phases)
+  using FR = typename AX::FR;
+  using FC = typename AX::FC;
+  static constexpr int G = AX::G;
+  static constexpr bool kBLK = AX::kBLK;
+  static constexpr bool kWL = AX::kWL;
   static constexpr int LDS = FR::LDS_ELEMS > FC::LDS_ELEMS ? FR::LDS_ELEMS : FC::LDS_ELEMS;
   static constexpr int QI = FR::template QF<+1>();
   static constexpr int QO = FR::template QL<+1>();
@@ -149,6 +153,13 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
   const bool pad_imag = V.half_last && pair == V.P - 1;
   using AC = ExAddr<FC, R::QA, true, NY, NX>;    // column phase, forward first / inverse last pass
   using AR = ExAddr<FR, R::QI, false, NX, NX>;   // row phase, inverse first / forward last pass
+  // Blocked exchange layout inside the launch (as in the L1 model's resident
+  // kernel): the first column phase reads the [ny][nx] field and the last row
+  // phase writes it, each relayout behind one extra team barrier.
+  constexpr bool BLK = R::kBLK;
+  constexpr bool WL = R::kWL;
+  using ACB = ExBlk<FC, R::QA, true, NY, R::G>;
+  using ARB = ExBlk<FR, R::QI, false, NY, R::G>;
 
   unsigned phase = 0;
   bool ok = true;
@@ -158,28 +169,28 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
       {
         cpx<T> a[R::NQA][R::QA];
         cpx<T> b[R::NQB][R::QB];
-#pragma unroll
-        for (int q = 0; q < R::NQA; ++q) {
-          unsigned v;
-          if (AC::voff(tid, q, c0, v)) {
-#pragma unroll
-            for (int r = 0; r < R::QA; ++r) a[q][r] = buf_ld(rex, v, AC::soff(r));
-          }
+        const bool first = it == 0 && half == 0;
+        if constexpr (BLK) {
+          if (!first) ex_load<ACB>(a, rex, tid, c0);
+          else ex_load<AC>(a, rex, tid, c0);
+        } else {
+          ex_load<AC>(a, rex, tid, c0);
         }
-        FC::template run<-1>(a, b, lds, twy, tid);
+        FC::template run<-1, BLK>(a, b, lds, twy, tid);
 #pragma unroll
         for (int q = 0; q < R::NQB; ++q)
 #pragma unroll
           for (int r = 0; r < R::QB; ++r) b[q][r] = mk(dk[q][r] * b[q][r].x, dk[q][r] * b[q][r].y);
-        FC::sync_before_reuse();
-        FC::template run<+1>(b, a, lds, twy, tid);
-#pragma unroll
-        for (int q = 0; q < R::NQA; ++q) {
-          unsigned v;
-          if (AC::voff(tid, q, c0, v)) {
-#pragma unroll
-            for (int r = 0; r < R::QA; ++r) buf_st(rex, v, AC::soff(r), a[q][r]);
+        FC::template sync_before_reuse<BLK>();
+        FC::template run<+1, BLK>(b, a, lds, twy, tid);
+        if constexpr (BLK) {
+          if (first) {
+            ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
+            if (!ok) break;
           }
+          ex_store<ACB>(a, rex, tid, c0);
+        } else {
+          ex_store<AC>(a, rex, tid, c0);
         }
       }
       ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
@@ -189,15 +200,9 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
       {
         cpx<T> a[R::NQI][R::QI];
         cpx<T> b[R::NQO][R::QO];
-#pragma unroll
-        for (int q = 0; q < R::NQI; ++q) {
-          unsigned v;
-          if (AR::voff(tid, q, r0, v)) {
-#pragma unroll
-            for (int r = 0; r < R::QI; ++r) a[q][r] = buf_ld(rex, v, AR::soff(r));
-          }
-        }
-        FR::template run<+1>(a, b, lds, twx, tid);
+        if constexpr (BLK) ex_load<ARB>(a, rex, tid, r0);
+        else ex_load<AR>(a, rex, tid, r0);
+        FR::template run<+1, WL>(a, b, lds, twx, tid);
         if (half == 0) {
           // dual: u = D chibar_n in b
 #pragma unroll
@@ -269,15 +274,19 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
             }
         }
         if (!last_update) {
-          FR::sync_before_reuse();
-          FR::template run<-1>(b, a, lds, twx, tid);
-#pragma unroll
-          for (int q = 0; q < R::NQI; ++q) {
-            unsigned v;
-            if (AR::voff(tid, q, r0, v)) {
-#pragma unroll
-              for (int r = 0; r < R::QI; ++r) buf_st(rex, v, AR::soff(r), a[q][r]);
+          FR::template sync_before_reuse<WL>();
+          FR::template run<-1, WL>(b, a, lds, twx, tid);
+          const bool end = half == 1 && it == iters - 1;   // the launch's last exchange store
+          if constexpr (BLK) {
+            if (end) {
+              ok = team_barrier(cnt, (++phase) * TEAM, abort_flag, &lds_flag, fenced, spin_limit);
+              if (!ok) break;
+              ex_store<AR>(a, rex, tid, r0);
+            } else {
+              ex_store<ARB>(a, rex, tid, r0);
             }
+          } else {
+            ex_store<AR>(a, rex, tid, r0);
           }
         }
       }
