@@ -370,6 +370,31 @@ def test_resident_batch_split_across_launches(solver, torch_mod):
         _parity.check(got[z:z + 1], ref, "slice %d" % z)
 
 
+@pytest.mark.parametrize("n", [64, 256])
+def test_resident_short_launches_equal_one_launch(torch_mod, n):
+    """Inside a launch the resident kernel hands the half-transformed field
+    between its phases in a blocked layout and converts it to and from the
+    [ny][nx] layout at the launch's first and last iteration.  Launches of 1,
+    2 and 5 iterations (every iteration a boundary, with and without gap
+    checks at launch ends) give the bits of one launch over all iterations."""
+    import paper_2006_09808_amd as pd
+    for gap_tol, check_every in ((0.0, 10), (1e-12, 4)):
+        w, delta = make_case(81, 5, n, n, lam=1e-3, max_iter=12, gap_tol=gap_tol, check_every=check_every)
+        sp = w.solver_params()
+        with pd.Solver(arena_bytes=1 << 30, device=0) as s:
+            ref, iref = gpu_solve(s, torch_mod, delta, **sp)
+        for k in (1, 2, 5):
+            with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=k, time_kernels=True) as s:
+                got, info = gpu_solve(s, torch_mod, delta, **sp)
+                n_res, _, _ = s.kernel_time(pd.KIND_RESIDENT)
+            _say("%dx%d gap_tol %g, steps of %d: %d resident launches" % (n, n, gap_tol, k, n_res))
+            assert info["iterations"] == iref["iterations"] == 12 and n_res >= 12 // k
+            np.testing.assert_array_equal(got, ref)
+            assert info["primal"] == pytest.approx(iref["primal"], rel=1e-12)
+    ref_o, _ = oracle.solve(delta.astype(np.float64), **sp)
+    _parity.check(got, ref_o, "%dx%d short launches" % (n, n))
+
+
 @pytest.mark.parametrize("n", [64, 128, 192, 256])
 def test_resident_protocols_and_two_launch_path_agree(solver, solver_two, solver_fenced, torch_mod, n):
     """Same arithmetic in the same order: the XCD-local and fenced exchange

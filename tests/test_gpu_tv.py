@@ -284,3 +284,21 @@ def test_tv_resident_more_pairs_than_one_launch_and_short_steps(solver_two, torc
         _say("  steps of 7: %d resident launches" % n_res)
         assert info["status"] == 0 and info["iterations"] == 30 and n_res == 5
     np.testing.assert_array_equal(chi_r, chi_t)
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_tv_resident_single_iteration_launches(solver_two, torch_mod, n):
+    """Steps of 1 and 3 iterations on the shapes whose resident launch keeps
+    the exchange in a blocked layout inside the launch (converted at the
+    launch's first and last phase): the four-launch path's bits."""
+    import paper_2006_09808_amd as pd
+    w, delta, W, M = make_tv_case(99, 4, n, n, iters=7)
+    sp = w.solver_params()
+    chi_t, _ = gpu_tv_solve(solver_two, torch_mod, delta, W, M, **sp)
+    for k in (1, 3):
+        with pd.Solver(arena_bytes=1 << 30, device=0, step_iters=k, time_kernels=True) as s:
+            chi_r, info = gpu_tv_solve(s, torch_mod, delta, W, M, **sp)
+            n_res, _, _ = s.kernel_time(pd.KIND_TV_RESIDENT)
+        _say("  %dx%d steps of %d: %d resident launches" % (n, n, k, n_res))
+        assert info["status"] == 0 and info["iterations"] == 7 and n_res == -(-7 // k)
+        np.testing.assert_array_equal(chi_r, chi_t)
