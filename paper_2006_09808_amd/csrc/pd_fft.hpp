@@ -510,6 +510,7 @@ template <typename T, int M, int S, int NT, bool COLS>
 struct Blue {
   using F0 = Fft<T, M, S, NT, COLS>;
   static constexpr int kNT = NT;
+  static constexpr bool kWaveLocal = false;   // its chirp tables are shared across rows
   static constexpr int LDS_ELEMS = F0::LDS_ELEMS;
   static constexpr int L0 = F0::template QF<-1>();   // forward first-pass radix
   static constexpr int L1 = F0::template QL<-1>();   // forward last-pass radix
@@ -528,9 +529,10 @@ struct Blue {
   }
   static __device__ __forceinline__ int lidx(int s, int n) { return F0::lidx(s, n); }
 
-  template <int DIR>
+  template <int DIR, bool WL = false>
   static __device__ __forceinline__ void run(cpx<T> (&in)[nq<L0>()][L0], cpx<T> (&out)[nq<L0>()][L0], cpx<T>* lds,
                                              const cpx<T>* __restrict__ tw, int tid, int len) {
+    static_assert(!WL, "Bluestein transforms synchronise the workgroup");
     const cpx<T>* __restrict__ chirp = tw + M;
     const cpx<T>* __restrict__ bh = tw + M + len + (DIR < 0 ? 0 : M);
     // a_n = x_n c_n (conj(c_n) for the inverse), zero beyond len
@@ -564,7 +566,11 @@ struct Blue {
       }
   }
 
-  static __device__ __forceinline__ void sync_before_reuse() { __syncthreads(); }
+  template <bool WL = false>
+  static __device__ __forceinline__ void sync_before_reuse() {
+    static_assert(!WL, "Bluestein transforms synchronise the workgroup");
+    __syncthreads();
+  }
 };
 
 // Engine of a kernel's transform axis: EXT < 2 the plain length-N engine with

@@ -287,6 +287,9 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
   using F = AxisFft<T, NX, S, kThreads, false, EXT, PV>;
   constexpr int QI = F::template QF<+1>();  // inverse first radix == forward last radix
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
+  // one-radix plans: each row's transform stays inside one wave, so its
+  // passes need no workgroup barrier
+  constexpr bool WL = F::kWaveLocal;
   __shared__ cpx<T> lds[F::LDS_ELEMS];
   __shared__ cpx<T> tw_s[F::TW_MAX];
 
@@ -330,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
           b[q][r] = mk(in[o], pad_imag ? (T)0 : in[plane + o]);
         }
       }
-    F::template run<-1>(b, a, lds, tw, tid, len);
+    F::template run<-1, WL>(b, a, lds, tw, tid, len);
     cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
     for (int q = 0; q < F::template nq<QI>(); ++q)
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
           if (F::template pos<QO>(tid, q, r, s, n) && inb(s, n)) c[q][r] = chi0[(size_t)s * len + n];
         }
     }
-    F::template run<+1>(a, b, lds, tw, tid, len);
+    F::template run<+1, WL>(a, b, lds, tw, tid, len);
 
     if constexpr (MODE == ROW_INV_PLANAR) {
       T* __restrict__ out = gmem((T*)V.user_out) + slice0 * plane + (size_t)r0 * len;
@@ -432,8 +435,8 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
         }
       }
       if (!last) {
-        F::sync_before_reuse();
-        F::template run<-1>(b, a, lds, tw, tid, len);
+        F::template sync_before_reuse<WL>();
+        F::template run<-1, WL>(b, a, lds, tw, tid, len);
         cpx<T>* dst = gmem((cpx<T>*)V.ex) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)
@@ -444,8 +447,8 @@ __global__ __launch_bounds__(kThreads) void k_row(const Vol* __restrict__ vols,
           }
       }
       if (check) {
-        F::sync_before_reuse();
-        F::template run<-1>(c, a, lds, tw, tid, len);
+        F::template sync_before_reuse<WL>();
+        F::template run<-1, WL>(c, a, lds, tw, tid, len);
         cpx<T>* dst = gmem((cpx<T>*)V.ex2) + base;
 #pragma unroll
         for (int q = 0; q < F::template nq<QI>(); ++q)

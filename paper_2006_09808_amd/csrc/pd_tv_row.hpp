@@ -57,6 +57,9 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
   constexpr int QO = F::template QL<+1>();  // inverse last radix == forward first radix
   constexpr bool Z3 = MODE == ROW_TV3_DUAL || MODE == ROW_TV3_PRIMAL;
   constexpr bool DUAL = MODE == ROW_TV_DUAL || MODE == ROW_TV3_DUAL;
+  // one-radix plans: each row's transform stays inside one wave (the mirror
+  // split below keeps its own workgroup barriers)
+  constexpr bool WL = F::kWaveLocal;
   __shared__ cpx<T> lds[F::LDS_ELEMS];
   __shared__ cpx<T> tw_s[F::TW_MAX];
 
@@ -103,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
         }
       }
     }
-  F::template run<+1>(a, b, lds, tw, tid, len);
+  F::template run<+1, WL>(a, b, lds, tw, tid, len);
 
   const T sig = (T)V.sigma;
   const T idx = (T)V.inv_dx, idy = (T)V.inv_dy, idz = (T)V.inv_dz;
@@ -220,8 +223,8 @@ __global__ __launch_bounds__(kThreads) void k_row_tv(const Vol* __restrict__ vol
     store_ex = it != V.final_it;
   }
   if (store_ex) {
-    F::sync_before_reuse();
-    F::template run<-1>(b, a, lds, tw, tid, len);
+    F::template sync_before_reuse<WL>();
+    F::template run<-1, WL>(b, a, lds, tw, tid, len);
     if constexpr (Z3) {
       // split the pair's row spectrum into the two slices' spectra: Z(-k)
       // sits in another lane, so the row goes through LDS
