@@ -211,6 +211,12 @@ struct Resident {
   static constexpr int NQA = FC::template nq<QA>();
   static constexpr int NQB = FC::template nq<QB>();
   static constexpr bool kWL = AX::kWL;
+  // waves per SIMD the register allocation must allow (the launch bound's
+  // second argument): two wherever the member's state fits in 256 registers
+  // per lane, so that a variant's co-resident capacity does not hinge on the
+  // allocator landing one register under the limit; the 192x192 variants and
+  // the 8 x 8 x 4 plan at 256x256 need more and run at one wave per SIMD
+  static constexpr int kMinWaves = (NX == 192 || (NX == 256 && PV == 1)) ? 1 : 2;
   static constexpr int kTeam = TEAM;
   static constexpr int kThreadsPerGroup = NT;
   // shared memory of one team member, carved from one byte buffer: the FFT
@@ -290,7 +296,7 @@ __device__ __forceinline__ bool form_team(unsigned* counters, int ticket_base, i
 }
 
 template <int NX, int NY, int TEAM, int NT, int PV>
-__global__ __launch_bounds__(NT) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
+__global__ __launch_bounds__(NT, (Resident<NX, NY, TEAM, NT, PV>::kMinWaves)) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
                                                  int* __restrict__ abort_flag, int nteams, int force_fenced,
                                                  unsigned spin_limit) {
