@@ -304,11 +304,12 @@ TV_BYTES_PER_VOXEL_IT = 96.0
 TV_COL_BYTES_PER_POINT = 16.0
 TV_ROW_BYTES_PER_POINT = 80.0       # mean of the dual (96) and primal (64) row kernels
 # the TV model's resident launch (square slices): the exchange field stays in
-# the L2 of the team's XCD, so per iteration HBM sees the row phases' state
-# only: dual reads p, W, delta, chibar, M, q_x, q_y and writes p, q_x, q_y
-# (80); primal reads chi, q_x, q_y, M and writes chi, chibar (48): 128 B per
-# slice-pair point, 64 B per voxel-iteration
-TV_RES_BYTES_PER_POINT_IT = 128.0
+# the L2 of the team's XCD and the mask M in LDS for the whole launch, so per
+# iteration HBM sees the row phases' other state only: dual reads p, W,
+# delta, chibar, q_x, q_y and writes p, q_x, q_y (72); primal reads chi, q_x,
+# q_y and writes chi, chibar (40): 112 B per slice-pair point, 56 B per
+# voxel-iteration
+TV_RES_BYTES_PER_POINT_IT = 112.0
 
 
 def tv_workload(nz=64, n=256, iters=500, reps=3):

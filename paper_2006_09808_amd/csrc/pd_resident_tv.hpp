@@ -13,7 +13,10 @@
 // row halves on its RT rows.  Unlike the L1 model the TV model's state (chi,
 // chibar, p, q_x, q_y, W, M, delta: seven image-domain fields per slice and
 // the exchange) does not fit on chip, so the row phases stream it from and
-// to HBM as the two-launch row kernels do.  One iteration:
+// to HBM as the two-launch row kernels do, except the mask M: constant and
+// read by both row phases, it is staged once per launch in LDS for the
+// member's rows and the row above them (the primal phase's G* reads it).
+// One iteration:
 //
 //   column phase  X' <- F_y^-1 (D / (nx ny)) F_y X'      (X' = F_x chibar_n)
 //   row phase     u = F_x^-1 X' = D chibar_n
@@ -68,9 +71,11 @@ struct ResidentTv {
   static constexpr int NQB = FC::template nq<QB>();
   static constexpr int kTeam = TEAM;
   static constexpr int kThreadsPerGroup = NT;
-  // shared memory: FFT staging, the twiddles of both axes, the barrier flag
+  // shared memory: FFT staging, the twiddles of both axes, M of rows
+  // r0 - 1 .. r0 + RT - 1 ([RT + 1][NX], slot 0 the row above), the barrier flag
   static constexpr size_t OFF_TW = (size_t)LDS * sizeof(cpx<float>);
-  static constexpr size_t OFF_FLAG = OFF_TW + (size_t)(NX + NY) * sizeof(cpx<float>);
+  static constexpr size_t OFF_M = OFF_TW + (size_t)(NX + NY) * sizeof(cpx<float>);
+  static constexpr size_t OFF_FLAG = OFF_M + (size_t)(RT + 1) * NX * sizeof(cpx<float>);
   static constexpr size_t SMEM = OFF_FLAG + 16;
   static_assert(NX == NY, "square slices");
 
@@ -109,6 +114,7 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
   using T = float;
   cpx<T>* lds = (cpx<T>*)(smem);
   cpx<T>* tw_s = (cpx<T>*)(smem + OFF_TW);
+  cpx<T>* m_s = (cpx<T>*)(smem + OFF_M);
   int& lds_flag = *(int*)(smem + OFF_FLAG);
   const int tid = threadIdx.x;
   const int iters = V.iters;
@@ -145,7 +151,12 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
       dk[q][r] = (T)0;
       if (FC::template pos<R::QB>(tid, q, r, s, n)) dk[q][r] = dtab[(unsigned)(n * NX + c0 + s)] * invN;
     }
-  __syncthreads();   // twiddle tables staged
+  // M of rows r0 - 1 .. r0 + RT - 1 (no row above the first member's rows)
+  for (int i = tid; i < (R::RT + 1) * NX; i += NT) {
+    const int row = r0 - 1 + i / NX;
+    if (row >= 0) m_s[i] = st_ld(rm, (unsigned)((row * NX + i % NX) * 8));
+  }
+  __syncthreads();   // twiddle tables and M staged
 
   const T sig = (T)V.sigma, damp = (T)(1.0 / (1.0 + V.sigma / V.lam));
   const T tau = (T)V.tau, theta = (T)V.theta;
@@ -220,7 +231,7 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
                 const cpx<T> c0v = st_ld(rcb, o);
                 const cpx<T> cr = n + 1 < NX ? st_ld(rcb, o + 8) : c0v;
                 const cpx<T> cd = row + 1 < NY ? st_ld(rcb, o + NX * 8) : c0v;
-                const cpx<T> mm = st_ld(rm, o), qx0 = st_ld(rqx, o), qy0 = st_ld(rqy, o);
+                const cpx<T> mm = m_s[(s + 1) * NX + n], qx0 = st_ld(rqx, o), qy0 = st_ld(rqy, o);
                 const T vxa = qx0.x + sig * mm.x * ((cr.x - c0v.x) * idx);
                 const T vya = qy0.x + sig * mm.x * ((cd.x - c0v.x) * idy);
                 const T vxb = qx0.y + sig * mm.y * ((cr.y - c0v.y) * idx);
@@ -244,14 +255,14 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
                 const unsigned o = (unsigned)((row * NX + n) * 8);
                 const cpx<T> x0 = st_ld(rchi, o), u = b[q][r];
                 // G* (M q): element i takes +(M q)[i-1] and -(M q)[i] per axis
-                const cpx<T> m0 = st_ld(rm, o), qx0 = st_ld(rqx, o), qy0 = st_ld(rqy, o);
+                const cpx<T> m0 = m_s[(s + 1) * NX + n], qx0 = st_ld(rqx, o), qy0 = st_ld(rqy, o);
                 T ta = 0, tb = 0;
                 if (n + 1 < NX) {
                   ta -= m0.x * qx0.x * idx;
                   tb -= m0.y * qx0.y * idx;
                 }
                 if (n >= 1) {
-                  const cpx<T> ml = st_ld(rm, o - 8), ql = st_ld(rqx, o - 8);
+                  const cpx<T> ml = m_s[(s + 1) * NX + n - 1], ql = st_ld(rqx, o - 8);
                   ta += ml.x * ql.x * idx;
                   tb += ml.y * ql.y * idx;
                 }
@@ -260,7 +271,7 @@ __device__ __forceinline__ void ResidentTv<NX, NY, TEAM, NT, PV>::run(unsigned c
                   tb -= m0.y * qy0.y * idy;
                 }
                 if (row >= 1) {
-                  const cpx<T> mu = st_ld(rm, o - NX * 8), qu = st_ld(rqy, o - NX * 8);
+                  const cpx<T> mu = m_s[s * NX + n], qu = st_ld(rqy, o - NX * 8);
                   ta += mu.x * qu.x * idy;
                   tb += mu.y * qu.y * idy;
                 }
