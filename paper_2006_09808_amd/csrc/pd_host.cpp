@@ -457,6 +457,7 @@ struct Job {
   Table tab{};              // copy of the shared table's device pointers
   int done_iters = 0;
   int run_iters = 0;        // iterations enqueued for it in the current round
+  bool chi_stored = false;  // its result store is enqueued in the current round
   bool finished = false;
   bool in_resident = false; // some resident launch of the current round covers it
   double knorm = 0.0;       // max |D| of the request's kernel grid
@@ -1514,6 +1515,7 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
   for (auto& j : act) {
     j->run_iters = 0;
     j->in_resident = false;
+    j->chi_stored = false;
   }
   StepEvents tev;
   hipError_t e = hipSuccess;
@@ -1524,6 +1526,18 @@ hipError_t run_step(pd_ctx* c, std::vector<std::shared_ptr<Job>>& act, bool queu
     if ((e = enqueue_step(c, act, queued, c->h_stage[s], tev, K, last)) != hipSuccess) break;
     total += K;
     if (last || queued || total >= kRunAheadIters) break;
+  }
+  // A job whose last iteration is in this round ends in it, whatever its
+  // checks decide on the way (a volume stopped earlier keeps its chi), so
+  // its result store goes into the round too, before the one wait: the
+  // retirement then needs no second round trip.  (Should the round abort, the
+  // restarted request stores its result again when it really ends.)
+  for (auto& j : act) {
+    if (e != hipSuccess) break;
+    if (j->req.max_iter > 0 && j->done_iters + j->run_iters >= j->req.max_iter) {
+      e = launch_store_chi(c->d_vols, j->slot, (size_t)j->L.P * j->req.nx * j->req.ny, c->precision, c->stream);
+      j->chi_stored = e == hipSuccess;
+    }
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->h_ctl, c->d_ctl, c->off_abort + sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -1662,6 +1676,7 @@ void worker_main(pd_ctx* c) {
       bool aborted = false;
       e = run_step(c, act, queued, &aborted);
       if (e == hipSuccess && aborted) e = recover_round(c, act, restarted);
+      bool need_sync = false;   // a store launched after the round's wait
       if (e == hipSuccess) {
         for (auto& j : act) {
           if (std::find(restarted.begin(), restarted.end(), j) != restarted.end()) continue;
@@ -1683,16 +1698,18 @@ void worker_main(pd_ctx* c) {
               e = hipMemsetAsync(j->req.chi, 0,
                                  (size_t)j->req.nx * j->req.ny * j->req.nz * (c->precision == PD_FP64 ? 8 : 4),
                                  c->stream);
-            } else {
+              need_sync = true;
+            } else if (!j->chi_stored) {   // stopped by a check before its last iteration
               e = launch_store_chi(c->d_vols, j->slot, (size_t)j->L.P * j->req.nx * j->req.ny, c->precision,
                                    c->stream);
+              need_sync = true;
             }
             if (e != hipSuccess) break;
           } else {
             j->done_iters += j->run_iters;
           }
         }
-        if (e == hipSuccess && !retired.empty()) e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess && need_sync) e = hipStreamSynchronize(c->stream);
       }
     }
     lk.lock();
