@@ -34,6 +34,7 @@ PD_DECL(768)
   int resident_plan_##N##_##V();
 #define PD_RES_LIST(X)                                                                                  \
   X(64, 0) X(64, 1) X(64, 2) X(128, 0) X(128, 1) X(128, 2) X(128, 3) X(128, 4) X(192, 0) X(192, 1)    \
+  X(192, 2) X(192, 3)                                                                                   \
   X(256, 0) X(256, 1) X(256, 2) X(256, 3)
 PD_RES_LIST(PD_DECL_RES)
 #undef PD_DECL_RES

@@ -295,8 +295,12 @@ __device__ __forceinline__ bool form_team(unsigned* counters, int ticket_base, i
   return true;
 }
 
-template <int NX, int NY, int TEAM, int NT, int PV>
-__global__ __launch_bounds__(NT, (Resident<NX, NY, TEAM, NT, PV>::kMinWaves)) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
+// MW: waves per SIMD the register allocation must allow (0: the variant's
+// kMinWaves).  A 192x192 variant with MW = 2 spills part of its state to
+// scratch but holds twice the pairs of its one-wave twin: the faster choice
+// once a step's pairs exceed what one launch of the twin holds.
+template <int NX, int NY, int TEAM, int NT, int PV, int MW = 0>
+__global__ __launch_bounds__(NT, (MW > 0 ? MW : Resident<NX, NY, TEAM, NT, PV>::kMinWaves)) void k_resident(const Vol* __restrict__ vols, const Range* __restrict__ ranges,
                                                  int nranges, Ctl* __restrict__ ctl, unsigned* __restrict__ counters,
                                                  int* __restrict__ abort_flag, int nteams, int force_fenced,
                                                  unsigned spin_limit) {
@@ -636,23 +640,23 @@ __global__ __launch_bounds__(NT, 2) void k_resident_multi(const Vol* __restrict_
 // (grid = a multiple of 8 TEAM workgroups; the padding teams exit at once).
 // The caller keeps nteams within resident_max_teams, the co-resident
 // capacity.
-template <int NX, int NY, int TEAM, int NT, int PV>
+template <int NX, int NY, int TEAM, int NT, int PV, int MW = 0>
 hipError_t launch_resident_t(int nteams, const Vol* vols, const Range* ranges, int nranges, Ctl* ctl,
                              unsigned* counters, int* abort_flag, int fenced, unsigned spin_limit, hipStream_t st) {
   const int rounds = (nteams + kXcds - 1) / kXcds;
   const int grid = rounds * kXcds * TEAM;
-  hipLaunchKernelGGL((k_resident<NX, NY, TEAM, NT, PV>), dim3(grid), dim3(NT), 0, st, vols, ranges, nranges, ctl,
-                     counters, abort_flag, nteams, fenced, spin_limit);
+  hipLaunchKernelGGL((k_resident<NX, NY, TEAM, NT, PV, MW>), dim3(grid), dim3(NT), 0, st, vols, ranges, nranges,
+                     ctl, counters, abort_flag, nteams, fenced, spin_limit);
   return hipGetLastError();
 }
 
-template <int NX, int NY, int TEAM, int NT, int PV>
+template <int NX, int NY, int TEAM, int NT, int PV, int MW = 0>
 int resident_max_teams_t() {
   int per_cu = 0, dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_resident<NX, NY, TEAM, NT, PV>, NT, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_resident<NX, NY, TEAM, NT, PV, MW>, NT,
+                                                   0) != hipSuccess)
     return 0;
   int teams = per_cu * ncu / TEAM;
   return teams - teams % kXcds;
@@ -661,17 +665,19 @@ int resident_max_teams_t() {
 }  // namespace pdk
 
 // Defines resident variant V of the square N x N slice shape: its launcher,
-// its co-resident team capacity, its team size, block size and FFT pass plan.
-#define PD_INSTANTIATE_RESIDENT(N, V, TEAM, NT, PV)                                                      \
+// its co-resident team capacity, its team size, block size and FFT pass plan
+// (MW: the waves per SIMD its registers must allow, 0 for the default).
+#define PD_INSTANTIATE_RESIDENT_MW(N, V, TEAM, NT, PV, MW)                                              \
   namespace pdk {                                                                                        \
   hipError_t launch_resident_##N##_##V(int nteams, const Vol* vols, const Range* ranges, int nranges,    \
                                        Ctl* ctl, unsigned* counters, int* abort_flag, int fenced,        \
                                        unsigned spin_limit, hipStream_t st) {                            \
-    return launch_resident_t<N, N, TEAM, NT, PV>(nteams, vols, ranges, nranges, ctl, counters,           \
-                                                 abort_flag, fenced, spin_limit, st);                     \
+    return launch_resident_t<N, N, TEAM, NT, PV, MW>(nteams, vols, ranges, nranges, ctl, counters,       \
+                                                     abort_flag, fenced, spin_limit, st);                 \
   }                                                                                                      \
-  int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT, PV>(); }             \
+  int resident_max_teams_##N##_##V() { return resident_max_teams_t<N, N, TEAM, NT, PV, MW>(); }         \
   int resident_team_##N##_##V() { return TEAM; }                                                        \
   int resident_threads_##N##_##V() { return NT; }                                                       \
   int resident_plan_##N##_##V() { return PV; }                                                          \
   }
+#define PD_INSTANTIATE_RESIDENT(N, V, TEAM, NT, PV) PD_INSTANTIATE_RESIDENT_MW(N, V, TEAM, NT, PV, 0)
