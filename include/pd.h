@@ -318,7 +318,9 @@ typedef struct {
  * zero-filled volume of nz slices for `iters` iterations, then make the
  * fastest of each kind the context's choice for that shape:
  *   - resident-kernel variants (square FP32 shapes: workgroups per pair x
- *     threads per workgroup x FFT pass plan);
+ *     threads per workgroup x FFT pass plan; 192 x 192 has each of its two
+ *     shapes twice, variants 2 and 3 registered for two waves per SIMD: part
+ *     of the state spilled, twice the slice pairs per launch);
  *   - the two-launch path's column kernel per tile width and FFT pass plan of
  *     the length-ny transforms, and its row kernel per tile height and pass
  *     plan of the length-nx transforms, each timed alone.
