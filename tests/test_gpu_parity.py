@@ -497,6 +497,39 @@ def test_autotune_configurations_agree(torch_mod, n, nz):
             s.tune_set(nx, ny, -1, 0, 0, 5, 0)
 
 
+def test_192_joins_the_multi_shape_launch_and_equals_solo(torch_mod):
+    """A 192x192 volume runs as a body of the multi-shape launch next to a
+    256x256 one (its body spills to scratch at two waves per SIMD); both
+    equal their solo runs bitwise, and the oracle on sampled slices.  The solo
+    runs use the variants whose teams the bodies have (192: 12 x 256, 256:
+    16 x 256), so the FP64 gap partials are summed in the same order and the
+    gap is bitwise equal too."""
+    import paper_2006_09808_amd as pd
+    torch = torch_mod
+    cases = [make_case(1211, 6, 192, 192, lam=1e-3, max_iter=40, gap_tol=1e-12, check_every=20),
+             make_case(1212, 4, 256, 256, lam=1e-3, max_iter=40)]
+    with pd.Solver(arena_bytes=1 << 30, device=0, time_kernels=True) as s:
+        s.tune_set(192, 192, 0)
+        s.tune_set(256, 256, 1)
+        solo = [gpu_solve(s, torch, d, **w.solver_params()) for w, d in cases]
+        s.kernel_time_reset()
+        ins = [torch.from_numpy(d).to("cuda:0") for _, d in cases]
+        outs = [torch.empty_like(x) for x in ins]
+        ts = s.submit([(x, o, w.solver_params()) for x, o, (w, _) in zip(ins, outs, cases)])
+        infos = [s.poll(t, -1) for t in ts]
+        n_multi, _, _ = s.kernel_time(pd.KIND_MULTI)
+        n_single, _, _ = s.kernel_time(pd.KIND_RESIDENT)
+    _say("multi-shape launches %d, single-shape resident launches %d" % (n_multi, n_single))
+    assert n_multi >= 1 and n_single == 0
+    for (w, d), o, info, (chi_solo, info_solo) in zip(cases, outs, infos, solo):
+        assert info["status"] == pd.PD_OK and info["iterations"] == info_solo["iterations"]
+        got = o.cpu().numpy().astype(np.float64)
+        np.testing.assert_array_equal(got, chi_solo)
+        assert info["primal"] == info_solo["primal"]
+        ref, _ = oracle.solve(d[:2].astype(np.float64), **w.solver_params())
+        _parity.check(got[:2], ref, "%dx%d slices 0-1" % (d.shape[1], d.shape[2]))
+
+
 @pytest.mark.parametrize("v128", [0, 4])
 def test_uneven_shapes_share_one_launch_and_equal_solo(torch_mod, v128):
     """Volumes of 64x64, 128x128 and 256x256 submitted together run as teams
@@ -512,6 +545,7 @@ def test_uneven_shapes_share_one_launch_and_equal_solo(torch_mod, v128):
              make_case(1203, 7, 256, 256, lam=1e-3, max_iter=50)]
     with pd.Solver(arena_bytes=1 << 30, device=0, time_kernels=True) as s:
         s.tune_set(128, 128, v128)
+        s.tune_set(256, 256, 1)   # the team structure of the 256x256 body: the gap sums in the same order
         solo = [gpu_solve(s, torch, d, **w.solver_params()) for w, d in cases]
         s.kernel_time_reset()
         ins = [torch.from_numpy(d).to("cuda:0") for _, d in cases]
